@@ -1,0 +1,515 @@
+"""Pins of the oracle against facts that do not come from the oracle itself:
+thermodynamic identities and textbook entropies, element/mass conservation,
+detailed balance at equilibrium, the closed-form spectral radius, free-stream
+preservation and mirror symmetry, brute-force dense solves of the LU-SGS
+factorisation, the closed-form consistency-correction sums, and special cases
+that reduce to textbook schemes."""
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2403_03440_amd import inputs as I
+
+
+def make(mech, ni=4, nj=3, bc_mode=0, grid=None, T_inf=250.0, u_inf=5000.0):
+    x, y = grid if grid is not None else I.polar_grid(ni, nj)
+    cfg = I.Config("t", ni, nj, "air5", mech.two_temp, 10.0, u_inf, T_inf=T_inf)
+    Y = np.zeros(mech.ns)
+    Y[0] = 0.767
+    Y[1] = 0.233
+    fs = (1e-3 * Y, u_inf, 0.0, T_inf, T_inf)
+    o = orc.setup((x, y), mech, fs, bc_mode=bc_mode)
+    return o, cfg, fs
+
+
+def random_state(o, mech, n, seed, **kw):
+    return o.prim_to_cons(*I.random_prims(mech, n, seed, **kw))
+
+
+# ------------------------------------------------------------------ thermo
+@pytest.mark.parametrize("two_temp", [0, 1])
+def test_cv_is_de_dT(two_temp):
+    m = I.air11(two_temp)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    for T in (300.0, 2500.0, 9000.0):
+        e, h, cv, g = o.point_thermo(T)
+        ep = o.point_thermo(T * (1 + 1e-6))[0]
+        em = o.point_thermo(T * (1 - 1e-6))[0]
+        fd = (ep - em) / (2e-6 * T)
+        assert np.allclose(cv, fd, rtol=1e-7, atol=1e-9 * np.abs(cv).max())
+
+
+def test_gibbs_helmholtz():
+    """d(G/RT)/dT = -H/(R T^2) with H the molar enthalpy (all modes at T)."""
+    m = I.air11(0)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    for T in (500.0, 4000.0, 12000.0):
+        e, h, cv, g = o.point_thermo(T)
+        gp = o.point_thermo(T * (1 + 1e-6))[3]
+        gm = o.point_thermo(T * (1 - 1e-6))[3]
+        dg = (gp - gm) / (2e-6 * T)
+        H = h * m.M
+        assert np.allclose(dg, -H / (I.R_U * T * T), rtol=1e-6, atol=1e-12)
+
+
+def test_standard_entropies_textbook():
+    """Standard molar entropies of N2 and O2 at 298.15 K from the rigid-rotor /
+    harmonic-oscillator partition function: 191.6 and 205.1 J/(mol K) (textbook
+    values; pins the translational, rotational and electronic terms)."""
+    m = I.air5(0)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    T = 298.15
+    e, h, cv, g = o.point_thermo(T)
+    S = (h * m.M - g * I.R_U * T - m.h_form) / T + m.h_form / T
+    # S = (H - G)/T with H and G on the same 0 K reference
+    S = (h * m.M - g * I.R_U * T) / T
+    assert abs(S[0] - 191.6) < 0.5
+    assert abs(S[1] - 205.1) < 0.5
+
+
+@pytest.mark.parametrize("two_temp", [0, 1])
+def test_prim_roundtrip(two_temp):
+    m = I.air11(two_temp)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    rs, u, v, T, Tv = I.random_prims(m, 50, seed=3, T_range=(260.0, 20000.0))
+    q = o.prim_to_cons(rs, u, v, T, Tv)
+    for k in range(50):
+        Tk, Tvk, p, c = o.point_prim(q[:, k])
+        assert abs(Tk - T[k]) <= 1e-12 * T[k] * 50
+        assert abs(Tvk - Tv[k]) <= 1e-9 * Tv[k]
+
+
+# ---------------------------------------------------------------- kinetics
+COMP5 = np.array([[2, 0], [0, 2], [1, 1], [1, 0], [0, 1]], float)  # N, O atoms of N2 O2 NO N O
+
+
+@pytest.mark.parametrize("two_temp", [0, 1])
+def test_mass_and_element_conservation(two_temp):
+    m = I.air5(two_temp)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    rs, u, v, T, Tv = I.random_prims(m, 40, seed=5, T_range=(2000.0, 15000.0))
+    for k in range(40):
+        om, ov = o.point_production(rs[:, k], T[k], Tv[k])
+        scale = np.abs(om).sum()
+        assert abs(om.sum()) <= 1e-14 * scale * 10
+        elem = (om / m.M) @ COMP5
+        assert np.all(np.abs(elem) <= 1e-13 * (np.abs(om) / m.M).sum())
+
+
+def test_charge_conservation_ionised():
+    m = I.air11(1)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    charge = np.array([0, 0, 0, 0, 0, 1, 1, 1, 1, 1, -1], float)
+    rs, u, v, T, Tv = I.random_prims(m, 30, seed=7, T_range=(4000.0, 20000.0))
+    for k in range(30):
+        om, _ = o.point_production(rs[:, k], T[k], Tv[k])
+        zs = (om / m.M) * charge
+        assert abs(zs.sum()) <= 1e-13 * np.abs(zs).sum() + 1e-300
+        assert abs(om.sum()) <= 1e-13 * np.abs(om).sum()
+
+
+def test_toy_equilibrium_quadratic():
+    """A2 + M <=> 2A + M: with Kc = exp(-dG/RT) (p0/RT) the equilibrium
+    concentration of A solves [A]^2 + (Kc/2)[A] - Kc n/2 = 0 (n = atoms/volume);
+    the net production there vanishes."""
+    m = I.toy_dissociation(0)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    for T in (3000.0, 4500.0, 6000.0):
+        g = o.point_thermo(T)[3]
+        Kc = np.exp(-(2 * g[1] - g[0])) * (1e5 / (I.R_U * T))
+        n = 2 * 0.01 / m.M[0]
+        XA = (-Kc / 2 + np.sqrt(Kc * Kc / 4 + 2 * Kc * n)) / 2
+        XA2 = (n - XA) / 2
+        rs = np.array([XA2 * m.M[0], XA * m.M[1]])
+        om, _ = o.point_production(rs, T)
+        # forward rate alone as the scale
+        rs_f = np.array([rs[0], 0.0])
+        omf, _ = o.point_production(rs_f, T)
+        assert np.abs(om).max() <= 1e-10 * np.abs(omf).max()
+
+
+def test_detailed_balance_air5():
+    """After integrating the kinetics to steady state at fixed T (one
+    temperature), each reaction satisfies mass action with Kc from the Gibbs
+    energies, and omega_ve vanishes at T = Tv (two-temperature model)."""
+    from scipy.integrate import solve_ivp
+    m = I.air5(0)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    T = 6000.0
+    r0 = np.array([0.767, 0.233, 0, 0, 0]) * 0.01
+    sol = solve_ivp(lambda t, r: o.point_production(r, T)[0], (0, 1.0), r0, method="BDF", rtol=1e-12,
+                    atol=1e-18)
+    req = sol.y[:, -1]
+    om, _ = o.point_production(req, T)
+    scale = np.abs(o.point_production(np.array([0.767, 0.233, 0, 0, 0]) * 0.01, T)[0]).max()
+    assert np.abs(om).max() <= 1e-8 * scale
+    g = o.point_thermo(T)[3]
+    X = req / m.M
+    for r in range(m.nr):
+        nu = m.nu_b[r] - m.nu_f[r]
+        lnKc = -(nu @ g) + nu.sum() * np.log(1e5 / (I.R_U * T))
+        lnQ = nu @ np.log(X)
+        assert abs(lnQ - lnKc) < 1e-5
+    m2 = I.air5(1)
+    o2 = orc.Oracle()
+    o2.set_mechanism(m2)
+    om2, ov = o2.point_production(req, T, T)
+    assert abs(ov) <= 1e-7 * np.abs(o2.point_production(r0, T, T)[1] if False else scale * 1e7)
+
+
+# ------------------------------------------------- EOS, flux Jacobian, radius
+@pytest.mark.parametrize("mech", ["air5_1T", "air5_2T", "air11_2T"])
+def test_flux_jacobian_eigenvalues(mech):
+    """Eigenvalues of the assembled A(n) are U-c, U (nv-2 times), U+c with the
+    oracle's frozen sound speed: the spectral radius is |U| + c in closed form."""
+    m = {"air5_1T": I.air5(0), "air5_2T": I.air5(1), "air11_2T": I.air11(1)}[mech]
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    q = random_state(o, m, 6, seed=11, T_range=(500.0, 12000.0), y_floor=0.01)
+    for k in range(6):
+        ang = 0.3 + k
+        nx, ny = np.cos(ang), np.sin(ang)
+        A = o.point_flux_jacobian(q[:, k], nx, ny)
+        T, Tv, p, c = o.point_prim(q[:, k])
+        rho = q[:m.ns, k].sum()
+        U = (q[m.ns, k] * nx + q[m.ns + 1, k] * ny) / rho
+        ev = np.sort(np.linalg.eigvals(A).real)
+        expect = np.sort(np.r_[U - c, U + c, np.full(m.nv - 2, U)])
+        assert np.allclose(ev, expect, rtol=0, atol=1e-8 * (abs(U) + c))
+
+
+def test_flux_jacobian_vs_finite_difference():
+    m = I.air5(1)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    q = random_state(o, m, 3, seed=2, T_range=(800.0, 9000.0), y_floor=0.02)[:, 0]
+    A = o.point_flux_jacobian(q, 0.6, 0.8)
+    for col in range(m.nv):
+        h = 1e-6 * max(abs(q[col]), 1e-4)
+        qp, qm = q.copy(), q.copy()
+        qp[col] += h
+        qm[col] -= h
+        fd = (o.point_flux(qp, 0.6, 0.8) - o.point_flux(qm, 0.6, 0.8)) / (2 * h)
+        assert np.allclose(A[:, col], fd, rtol=1e-5, atol=1e-6 * np.abs(A).max())
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_source_jacobian_vs_finite_difference(which):
+    m = I.air5(1)
+    o = orc.Oracle()
+    o.set_mechanism(m)
+    rs, u, v, T, Tv = I.random_prims(m, 1, seed=9, T_range=(6000.0, 8000.0), y_floor=0.05)
+    q = o.prim_to_cons(rs, u, v, T, Tv)[:, 0]
+    J = o.point_source_jacobian(q, which)
+    assert np.all(np.isfinite(J))
+    # finite differences of the same quantities through the public point functions
+    ns, nf = m.ns, m.nf
+
+    def src(qq):
+        Tq, Tvq, p, c = o.point_prim(qq)
+        om, ov = o.point_production(qq[:ns], Tq, Tvq)
+        return om, ov
+
+    if which == 1:
+        for col in range(ns):
+            h = 1e-6 * q[col]
+            rp, rm = q[:ns].copy(), q[:ns].copy()
+            rp[col] += h
+            rm[col] -= h
+            fd = (o.point_production(rp, T[0], Tv[0])[0] - o.point_production(rm, T[0], Tv[0])[0]) / (2 * h)
+            assert np.allclose(J[:, col], fd, rtol=1e-5, atol=1e-6 * np.abs(J).max())
+    elif which == 2:
+        rho = q[:ns].sum()
+        Y = q[:ns] / rho
+        QF = np.r_[rho, q[ns:]]
+        for col in range(nf):
+            h = 1e-6 * max(abs(QF[col]), 1e-3)
+            out = []
+            for sgn in (1, -1):
+                Qp = QF.copy()
+                Qp[col] += sgn * h
+                qq = np.r_[Y * Qp[0], Qp[1:]]
+                out.append(src(qq)[1])
+            fd = (out[0] - out[1]) / (2 * h)
+            assert abs(J[col] - fd) <= 1e-5 * abs(fd) + 1e-6 * np.abs(J).max()
+    else:
+        nb = m.nb
+        z = np.r_[q[:ns].sum(), q[ns:], q[:ns - 1]]
+
+        def z2q(zz):
+            rs_ = np.r_[zz[nf:], zz[0] - zz[nf:].sum()]
+            return np.r_[rs_, zz[1:nf]]
+
+        def sz(zz):
+            om, ov = src(z2q(zz))
+            return np.r_[om.sum(), 0, 0, 0, ov, om[:ns - 1]]
+
+        for col in range(nb):
+            h = 1e-6 * max(abs(z[col]), 1e-3)
+            zp, zm = z.copy(), z.copy()
+            zp[col] += h
+            zm[col] -= h
+            fd = (sz(zp) - sz(zm)) / (2 * h)
+            assert np.allclose(J[:, col], fd, rtol=1e-4, atol=1e-5 * np.abs(J).max())
+
+
+# ---------------------------------------------------------------- residual
+@pytest.mark.parametrize("two_temp", [0, 1])
+def test_free_stream_preservation(two_temp):
+    m = I.air5(two_temp)
+    x, y = I.polar_grid(12, 8)
+    o, cfg, fs = make(m, grid=(x, y), bc_mode=1)
+    n = 12 * 8
+    q = o.prim_to_cons(np.repeat(fs[0][:, None], n, 1), np.full(n, fs[1]), np.zeros(n), np.full(n, 250.0),
+                       np.full(n, 250.0))
+    o.set_state(q)
+    o.residual(10.0)
+    R = o.get("R")
+    scale = 1e-3 * 5000.0 * 0.1  # rho u L
+    assert np.abs(R[:m.ns]).max() <= 1e-13 * scale
+    assert np.abs(R[m.ns + 2]).max() <= 1e-13 * scale * 5000.0 ** 2
+
+
+def test_mirror_symmetry():
+    m = I.air5(1)
+    o, cfg, fs = make(m, ni=16, nj=6)
+    n = 96
+    rs, u, v, T, Tv = I.random_prims(m, n, seed=4, T_range=(300.0, 3000.0), speed=500.0)
+    # make the field mirror-symmetric about theta = pi (i -> ni-1-i, v -> -v)
+    def sym(a, odd=False):
+        a = a.reshape(-1, 6, 16) if a.ndim == 2 else a.reshape(6, 16)
+        b = 0.5 * (a + (-1 if odd else 1) * a[..., ::-1])
+        return b.reshape(a.shape[0], -1) if a.ndim == 3 else b.ravel()
+    rs, u, T, Tv = sym(rs), sym(u), sym(T), sym(Tv)
+    v = sym(v, odd=True)
+    o.set_state(o.prim_to_cons(rs, u, v, T, Tv))
+    o.residual(5.0)
+    R = o.get("R").reshape(m.nv, 6, 16)
+    for k in range(m.nv):
+        odd = k == m.ns + 1
+        d = R[k] - (-1 if odd else 1) * R[k][:, ::-1]
+        assert np.abs(d).max() <= 1e-11 * np.abs(R[k]).max() + 1e-300
+
+
+# ------------------------------------------------------------------ sweeps
+def _tiny(two_temp, ni, nj, seed, cfl=50.0, mech=None):
+    m = mech or I.air5(two_temp)
+    o, cfg, fs = make(m, ni=ni, nj=nj)
+    rs, u, v, T, Tv = I.random_prims(m, ni * nj, seed=seed, T_range=(2000.0, 8000.0), speed=2000.0,
+                                     y_floor=0.02)
+    o.set_state(o.prim_to_cons(rs, u, v, T, Tv))
+    o.residual(cfl)
+    return o, m
+
+
+@pytest.mark.parametrize("mode", [orc.COUPLED, orc.SPLIT])
+def test_hyperplane_equals_lexicographic(mode):
+    o, m = _tiny(1, 9, 7, seed=21)
+    o.implicit_op(mode, orc.HYPERPLANE)
+    a = o.get("dq", mode).copy()
+    s = o.get("dqs", mode).copy()
+    o.implicit_op(mode, orc.LEXICOGRAPHIC)
+    assert np.array_equal(a, o.get("dq", mode))
+    assert np.array_equal(s, o.get("dqs", mode))
+
+
+def _blockdiag_solve(D, rhs, nsol):
+    out = np.empty_like(rhs)
+    for p in range(rhs.size // nsol):
+        sl = slice(p * nsol, (p + 1) * nsol)
+        out[sl] = np.linalg.solve(D[sl, sl], rhs[sl])
+    return out
+
+
+@pytest.mark.parametrize("mode", [orc.COUPLED, orc.SPLIT])
+@pytest.mark.parametrize("shape", [(3, 2), (4, 3)])
+def test_sweeps_equal_dense_factorised_solve(mode, shape):
+    """The sweep result x satisfies (D+L) D^-1 (D+U) x = b, checked by dense
+    products on the assembled global matrices (backward error against the
+    magnitude of the terms; the unknowns span eight decades, so a global dense
+    solve would itself lose digits)."""
+    o, m = _tiny(1, shape[0], shape[1], seed=5)
+    D, L, U = o.dense_operator(mode)
+    nsol = o.nsol(mode)
+    b = np.random.default_rng(1).standard_normal((nsol, o.N))
+    x = o.sweep_rhs(mode, b).T.ravel()
+    y = o.get("dqs", mode).T.ravel()
+    bb = b.T.ravel()
+    # forward half (D+L) y = b and backward half (D+U) x = D y, by products only
+    r1 = (D + L) @ y - bb
+    r2 = (D + U) @ x - D @ y
+    s1 = np.abs(D + L) @ np.abs(y) + np.abs(bb)
+    s2 = np.abs(D + U) @ np.abs(x) + np.abs(D) @ np.abs(y)
+    assert np.all(np.abs(r1) <= 1e-13 * s1)
+    assert np.all(np.abs(r2) <= 1e-13 * s2)
+
+
+@pytest.mark.parametrize("mode", [orc.COUPLED, orc.SPLIT])
+def test_repeated_sgs_converges_to_unfactored_solve(mode):
+    """Defect-corrected LU-SGS iterations x <- x + LUSGS(b - (D+L+U) x) drive
+    the unfactored residual to rounding level."""
+    o, m = _tiny(0, 4, 3, seed=8, cfl=2.0)
+    D, L, U = o.dense_operator(mode)
+    A = D + L + U
+    nsol = o.nsol(mode)
+    b = np.random.default_rng(2).standard_normal((nsol, o.N))
+    xv = np.zeros(nsol * o.N)
+    for _ in range(200):
+        r = b.T.ravel() - A @ xv
+        dx = o.sweep_rhs(mode, r.reshape(o.N, nsol).T)
+        xv = xv + dx.T.ravel()
+    r = b.T.ravel() - A @ xv
+    scale = np.abs(A) @ np.abs(xv) + np.abs(b.T.ravel())
+    assert np.all(np.abs(r) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("mode", [orc.COUPLED, orc.SPLIT])
+def test_uniform_increment_interior_kernel(mode):
+    """On a uniform state the off-diagonal blocks of an interior cell cancel
+    its spectral and viscous diagonal terms for a uniform increment (the
+    half-splitting and the radii enter D and O with opposite signs and
+    sum_f S_f n_f = 0):  (D + L + U) x = (V/dtau) x on interior cells (no source)."""
+    m = I.air5(0).without_reactions()
+    x_, y_ = I.polar_grid(5, 4)
+    o, cfg, fs = make(m, grid=(x_, y_), bc_mode=1)
+    n = 20
+    q = o.prim_to_cons(np.repeat(fs[0][:, None], n, 1), np.full(n, 3000.0), np.full(n, 1000.0),
+                       np.full(n, 2000.0), np.full(n, 1500.0))
+    o.set_state(q)
+    o.residual(3.0)
+    D, L, U = o.dense_operator(mode)
+    nsol = o.nsol(mode)
+    xv = np.tile(np.random.default_rng(0).standard_normal(nsol), o.N)
+    y = (D + L + U) @ xv
+    scale = (np.abs(D) + np.abs(L) + np.abs(U)) @ np.abs(xv)
+    for j in range(1, 3):
+        for i in range(1, 4):
+            p = j * 5 + i
+            sl = slice(p * nsol, (p + 1) * nsol)
+            ratio = y[sl][0] / xv[sl][0]
+            assert ratio > 0
+            assert np.all(np.abs(y[sl] - ratio * xv[sl]) <= 1e-12 * scale[sl])
+
+
+def test_single_cell_point_implicit():
+    """1x1 grid: the sweeps reduce to the point-implicit update dQ = -D^-1 R."""
+    m = I.air5(1)
+    o, cfg, fs = make(m, ni=1, nj=1)
+    rs, u, v, T, Tv = I.random_prims(m, 1, seed=3, T_range=(5000.0, 7000.0), y_floor=0.05)
+    o.set_state(o.prim_to_cons(rs, u, v, T, Tv))
+    o.residual(20.0)
+    R = o.get("R")[:, 0]
+    DK = o.get("DK")[:, :, 0]
+    o.implicit_op(orc.COUPLED)
+    ns = m.ns
+    bz = -np.r_[R[:ns].sum(), R[ns:], R[:ns - 1]]
+    assert np.allclose(o.get("dq")[:, 0], np.linalg.solve(DK, bz), rtol=1e-12, atol=0)
+
+
+def test_small_cfl_is_explicit_euler():
+    """CFL -> 0: dQ -> -(dtau/V) R (explicit pseudo-time step; frozen chemistry so
+    that the O(CFL) remainder comes from the spectral terms only)."""
+    m = I.air5(0).without_reactions()
+    o, cfg, fs = make(m, ni=6, nj=4)
+    rs, u, v, T, Tv = I.random_prims(m, 24, seed=6, T_range=(1000.0, 3000.0), speed=1000.0)
+    o.set_state(o.prim_to_cons(rs, u, v, T, Tv))
+    x, y = I.polar_grid(6, 4)
+    # cell areas by the shoelace formula
+    V = np.zeros(24)
+    for j in range(4):
+        for i in range(6):
+            px = [x[j, i], x[j, i + 1], x[j + 1, i + 1], x[j + 1, i]]
+            py = [y[j, i], y[j, i + 1], y[j + 1, i + 1], y[j + 1, i]]
+            V[j * 6 + i] = 0.5 * abs(sum(px[k] * py[(k + 1) % 4] - px[(k + 1) % 4] * py[k] for k in range(4)))
+    for cfl in (1e-4, 1e-5):
+        o.residual(cfl)
+        R = o.get("R")
+        dt = o.get("dtau")
+        o.implicit_op(orc.SPLIT)
+        dq = o.get("dq", orc.SPLIT)
+        expl_species = -(dt / V) * R[:m.ns]
+        err = np.abs(dq[m.nf:] - expl_species).max() / np.abs(expl_species).max()
+        assert err < 10 * cfl
+        expl_rhoE = -(dt / V) * R[m.ns + 2]
+        err = np.abs(dq[3] - expl_rhoE).max() / np.abs(expl_rhoE).max()
+        assert err < 10 * cfl
+
+
+# -------------------------------------------------------------- corrections
+@pytest.mark.parametrize("kind", [orc.CC1, orc.CC2])
+def test_consistency_corrections(kind):
+    o, m = _tiny(0, 5, 4, seed=12, cfl=0.5, mech=I.air5(0).without_reactions())
+    q0 = o.get_state()
+    o.implicit_op(orc.SPLIT)
+    dq = o.get("dq", orc.SPLIT)
+    nclip = o.consistency_correct(orc.SPLIT, kind)
+    assert nclip == 0
+    q1 = o.get_state()
+    rho0 = q0[:m.ns].sum(0)
+    rho1 = q1[:m.ns].sum(0)
+    assert np.allclose(rho1, rho0 + dq[0], rtol=1e-15 * 4, atol=0)
+    Y1 = q1[:m.ns] / rho1
+    assert np.allclose(Y1.sum(0), 1.0, atol=4e-16 * m.ns)
+    if kind == orc.CC2:
+        t = q0[:m.ns] + dq[m.nf:]
+        assert np.allclose(Y1, t / t.sum(0), rtol=1e-14)
+    assert np.allclose(q1[m.ns:], q0[m.ns:] + dq[1:m.nf], rtol=1e-15, atol=1e-300)
+
+
+def test_cc1_identity_when_consistent():
+    o, m = _tiny(0, 3, 2, seed=13, cfl=0.5, mech=I.air5(0).without_reactions())
+    q0 = o.get_state()
+    b = np.zeros((m.nf + m.ns, o.N))
+    rng = np.random.default_rng(0)
+    ds = rng.uniform(-1e-6, 1e-6, (m.ns, o.N))
+    b[m.nf:] = ds
+    o.implicit_op(orc.SPLIT)
+    dq = o.get("dq", orc.SPLIT)
+    # make the flow density increment equal to the species sum: CC1 changes nothing
+    q_expect = q0[:m.ns] + dq[m.nf:]
+    o2, _ = _tiny(0, 3, 2, seed=13, cfl=0.5, mech=I.air5(0).without_reactions())
+    o2.implicit_op(orc.SPLIT)
+    # CC1 correction term W_s (drho - sum drho_s) is zero when drho == sum drho_s
+    W = q0[:m.ns] / q0[:m.ns].sum(0)
+    corr = W * (dq[0] - dq[m.nf:].sum(0))
+    o2.consistency_correct(orc.SPLIT, orc.CC1)
+    q1 = o2.get_state()
+    assert np.allclose(q1[:m.ns], q_expect + corr, rtol=1e-14)
+
+
+def test_coupled_closure():
+    o, m = _tiny(0, 4, 3, seed=14, cfl=0.5, mech=I.air5(0).without_reactions())
+    q0 = o.get_state()
+    o.implicit_op(orc.COUPLED)
+    dq = o.get("dq", orc.COUPLED)
+    o.consistency_correct(orc.COUPLED, orc.CLOSURE)
+    q1 = o.get_state()
+    nf = m.nf
+    assert np.allclose(q1[:m.ns - 1], q0[:m.ns - 1] + dq[nf:], rtol=1e-15)
+    assert np.allclose(q1[:m.ns].sum(0), q0[:m.ns].sum(0) + dq[0], rtol=4e-15)
+
+
+# ------------------------------------------------------------- fixed point
+def test_zero_residual_gives_zero_increment():
+    m = I.air5(1).without_reactions()
+    x, y = I.polar_grid(8, 5)
+    o, cfg, fs = make(m, grid=(x, y), bc_mode=1)
+    n = 40
+    o.set_state(o.prim_to_cons(np.repeat(fs[0][:, None], n, 1), np.full(n, 5000.0), np.zeros(n),
+                               np.full(n, 250.0), np.full(n, 250.0)))
+    o.residual(100.0)
+    for mode in (orc.COUPLED, orc.SPLIT):
+        o.implicit_op(mode)
+        dq = o.get("dq", mode)
+        qs = o.get_state()
+        mom = np.hypot(qs[m.ns], qs[m.ns + 1]).max()
+        scale = np.r_[qs[:m.ns].sum(0).max(), mom, mom, np.abs(qs[m.ns + 2]).max()]
+        assert np.all(np.abs(dq[:4]).max(1) <= 1e-13 * scale)
