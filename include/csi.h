@@ -1,0 +1,150 @@
+/* csi.h -- C-ABI of the MI355X (gfx950) component-splitting implicit solver.
+ *
+ * The library computes one pseudo-time iteration of the implicit scheme of
+ * the paper (Section 2.2, Eq. (linearizedimplicit), Eq. (implicitscheme),
+ * Eq. (ijkiterate) and the LU-SGS forward/backward sweeps; Section 2.3, the
+ * component-splitting method and its consistence corrections) for the 2D
+ * multicomponent reacting Navier-Stokes equations (Section 2.1, Eq. (govern),
+ * Eq. (flux)) on a structured grid, with hand-written HIP kernels.
+ *
+ * Conventions
+ *  - Every call returns an int status: CSI_OK (0) or a negative CSI_ERR_*.
+ *    csi_last_error() gives the text of the last error on that context.
+ *  - Host pointers are owned by the caller and copied on entry.  Device
+ *    pointers (workspace, state with on_device=1, surrogate buffers) are owned
+ *    by the caller; the library never allocates device memory.
+ *  - All work is enqueued on the HIP stream given to csi_create; calls that
+ *    return host data synchronise that stream.
+ *  - Stored state q is FP64 structure-of-arrays [nv][nj][ni] (i fastest),
+ *    q = (rho_1..rho_ns, rho u, rho v, rho E, [rho e_ve]),
+ *    nv = ns + 3 (one temperature) or ns + 4 (two temperatures).
+ *  - Increments: coupled [nb][N] in z = (rho, rho u, rho v, rho E, [rho e_ve],
+ *    rho_1..rho_{ns-1}), nb = nf + ns - 1; split [nf + ns][N] =
+ *    (rho, rho u, rho v, rho E, [rho e_ve] | rho_1..rho_ns); nf = 4 or 5.
+ *  - Call order: create -> set_grid -> set_mechanism -> set_freestream ->
+ *    workspace_bytes -> bind_workspace -> set_state -> residual /
+ *    implicit_op / consistency_correct / step.  set_grid or set_mechanism
+ *    after binding invalidates the binding (CSI_ERR_STATE until rebound).
+ */
+#ifndef CSI_H
+#define CSI_H
+#include <stddef.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CSI_OK = 0,
+  CSI_ERR_ARG = -1,       /* invalid argument or size */
+  CSI_ERR_STATE = -2,     /* call out of order / workspace not bound */
+  CSI_ERR_HIP = -3,       /* HIP runtime error */
+  CSI_ERR_NONFINITE = -4, /* non-physical or non-finite state; cell index in stats / csi_bad_cell */
+  CSI_ERR_SINGULAR = -5,  /* zero pivot in a diagonal block */
+  CSI_ERR_UNSUPPORTED = -6 /* species count / temperature model without a compiled kernel */
+};
+enum { CSI_COUPLED = 0, CSI_SPLIT = 1 };
+enum { CSI_FP64 = 0, CSI_MIXED = 1 }; /* MIXED: FP32 blocks and sweeps; FP64 residual, chemistry, corrections */
+enum { CSI_CLOSURE = 0, CSI_CC1 = 1, CSI_CC2 = 2 };
+enum { CSI_JAC_EXACT = 0, CSI_JAC_SURROGATE = 1 };
+
+typedef struct csi_ctx csi_ctx;
+
+/* Mechanism tables (host, copied).  Species kinds: 0 atom / atomic ion,
+ * 1 linear molecule / molecular ion, 2 electron.  Arrhenius A in SI units,
+ * k_f = A Tf^b exp(-theta/Tf) with Tf = T, sqrt(T Tv) or Tv (tctl 0/1/2);
+ * backward rates from equilibrium constants of the species' Gibbs energies.
+ * Limits: ns <= 32, nr <= 64, at most three reactant and three product
+ * molecules per reaction. */
+typedef struct {
+  int ns, nr, two_temp;
+  const double *M, *theta_v, *theta_r, *sigma, *g_el, *h_form, *sc, *lt_a, *lt_b; /* [ns] */
+  const int *kind;                                                              /* [ns] */
+  const double *A, *b, *theta;                                                  /* [nr] */
+  const int *tctl, *third;                                                      /* [nr] */
+  const int *nu_f, *nu_b;                                                       /* [nr*ns] */
+  const double *eff;                                                            /* [nr*ns] */
+  double mu_ref, T_ref, mu_exp;
+} csi_mechanism;
+
+typedef struct {
+  int mode;        /* CSI_COUPLED or CSI_SPLIT */
+  int precision;   /* CSI_FP64 or CSI_MIXED */
+  int kind;        /* CSI_CLOSURE (coupled), CSI_CC1 or CSI_CC2 (split) */
+  int jac;         /* CSI_JAC_EXACT or CSI_JAC_SURROGATE */
+  double cfl;      /* target CFL */
+  int cfl_ramp;    /* geometric ramp from 1 to cfl over this many iterations (0: none) */
+  int max_iter;    /* iterations to run */
+  double tol;      /* stop once r_rho / r_rho(iteration 0) <= tol (<= 0: run max_iter) */
+  int check_every; /* iterations between host checks of the stop / error flags */
+} csi_step_params;
+
+typedef struct {
+  int iters;       /* iterations run by this call */
+  int converged;   /* 1 if the tolerance was reached (iteration index in it_conv) */
+  int it_conv;
+  int n_clipped;   /* cells with a clipped partial density */
+  int bad_cell;    /* first non-physical cell, or -1 */
+  double r0, r_last;
+} csi_step_stats;
+
+int csi_create(csi_ctx **ctx, int device, void *hip_stream);
+int csi_destroy(csi_ctx *ctx);
+const char *csi_last_error(const csi_ctx *ctx);
+
+/* Grid nodes x_nodes, y_nodes: host [(nj+1)][(ni+1)], i fastest.  bc_mode 0:
+ * isothermal no-slip non-catalytic wall at j = 0 (T_wall), free-stream far
+ * field at j = nj, zero-gradient outflow at i = 0 and i = ni; bc_mode 1:
+ * free stream on all four sides. */
+int csi_set_grid(csi_ctx *ctx, int ni, int nj, const double *x_nodes, const double *y_nodes, double T_wall,
+                 int bc_mode);
+int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
+/* free stream from primitives (rho_s [ns] host, u, v, T, Tv) */
+int csi_set_freestream(csi_ctx *ctx, const double *rho_s, double u, double v, double T, double Tv);
+int csi_workspace_bytes(const csi_ctx *ctx, size_t *bytes);
+/* dev_ptr: device memory of at least csi_workspace_bytes, 256-byte aligned; caller owns it */
+int csi_bind_workspace(csi_ctx *ctx, void *dev_ptr, size_t bytes);
+int csi_set_state(csi_ctx *ctx, const double *q, int on_device);
+int csi_get_state(csi_ctx *ctx, double *q, int on_device);
+
+/* Residual R = sum_f F_f S_f - V S(Q) (Section 2.2, Eq. (iterate) in finite-
+ * volume form) with local time steps at this CFL (Eq. for Delta tau), face
+ * spectral radii and the chemical source.  norms (host, nullable):
+ * [r_rho, r_E] = L2 norms over cells of sum_s R_rho_s / V and R_E / V. */
+int csi_residual(csi_ctx *ctx, double cfl, double *norms);
+/* Diagonal blocks of `mode` in `precision` (Section 2.2: I_m = V/dtau I - V A_S
+ * plus the spectral and viscous radii; Section 2.3: flow radius |U|+c and
+ * species radius |U| for the split parts), their inverses, then the LU-SGS
+ * forward and backward sweeps on the last residual.  dQ stays in the
+ * workspace.  jac: CSI_JAC_EXACT (analytic source Jacobian) or
+ * CSI_JAC_SURROGATE (split species block from the installed network, exact
+ * fallback per cell when the diagonal-dominance check fails). */
+int csi_implicit_op(csi_ctx *ctx, int mode, int precision, int jac);
+/* closure (coupled) or CC1 / CC2 (split) and the FP64 update of Q (paper Section 2.3) */
+int csi_consistency_correct(csi_ctx *ctx, int kind);
+/* iterate: residual -> implicit_op -> consistency_correct, with a CFL ramp and stop test */
+int csi_step(csi_ctx *ctx, const csi_step_params *p, csi_step_stats *s);
+/* wall heat flux into the wall per wall cell (host [ni]) and its value at the stagnation line */
+int csi_wall_heat_flux(csi_ctx *ctx, double *qw, double *q_stag);
+/* residual-norm history of csi_step calls: host [2*n] (r_rho, r_E per iteration) */
+int csi_norm_history(csi_ctx *ctx, int n, double *hist);
+
+/* Conservative state from primitives with the library's thermodynamics (host
+ * arrays): rho_s [ns][n], u, v, T, Tv [n] -> q [nv][n] */
+int csi_prim_to_cons(csi_ctx *ctx, int n, const double *rho_s, const double *u, const double *v, const double *T,
+                     const double *Tv, double *q);
+/* Phase timing of csi_step with HIP events on the context's stream (on = 1 to
+ * enable).  csi_phase_times returns the accumulated milliseconds of the
+ * phases [prim, faces, cell, norms, sweeps, update] and the number of timed
+ * iterations in ms[6]; reset = 1 clears the accumulators. */
+int csi_set_timing(csi_ctx *ctx, int on);
+int csi_phase_times(csi_ctx *ctx, double *ms, int reset);
+
+/* Debug / parity access to named workspace arrays, copied to host as FP64:
+ * "R" [nv][N], "dtau" [N], "src" [nv][N], "b" "dqs" "dq" [nsol][N], "T" "Tv" "p" "c" [N],
+ * "qw" [ni], "Dinv" (coupled [nb*nb][N]; split [6 + ns*ns][N]). */
+int csi_get_array(csi_ctx *ctx, const char *name, double *out, size_t count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -37,7 +37,8 @@ struct Face {
   double lvF = 0, lvC = 0, lvK = 0;   // viscous radii nu_f S_f / V_f (flow, species, coupled)
 };
 
-constexpr double CSTEP = 1e-25;  // complex-step size (relative to max(|x|, 1))
+constexpr double CSTEP = 1e-25;
+constexpr double TV_FLOOR = 50.0;  // lower bound of Tv after an update  // complex-step size (relative to max(|x|, 1))
 
 }  // namespace
 
@@ -989,7 +990,13 @@ int orc_consistency_correct(orc_ctx *c, int mode, int kind, int *n_clipped) {
     c->q[size_t(ns) * N + p] += dq(1);
     c->q[size_t(ns + 1) * N + p] += dq(2);
     c->q[size_t(ns + 2) * N + p] += dq(3);
-    if (m.two_temp) c->q[size_t(ns + 3) * N + p] += dq(4);
+    if (m.two_temp) {
+      // positivity of the vibrational-electronic energy: floor at Tv = 50 K
+      double eve = c->q[size_t(ns + 3) * N + p] + dq(4), floor_ = 0.0;
+      for (int s = 0; s < ns; ++s) floor_ += nr[s] * e_ve<double>(m, s, TV_FLOOR);
+      if (eve < floor_) { eve = floor_; if (!clip) ++clipped; }
+      c->q[size_t(ns + 3) * N + p] = eve;
+    }
   }
   if (n_clipped) *n_clipped = clipped;
   c->has_res = false;
@@ -1037,6 +1044,7 @@ int orc_get(orc_ctx *c, const char *name, double *out) {
   const int N = c->N;
   if (n == "R") return put(c->R);
   if (n == "dtau") return put(c->dtau);
+  if (n == "V") return put(c->V);
   if (n == "omega") return put(c->src);
   if (n == "dqs") return put(c->dqs);
   if (n == "dq") return put(c->dq);

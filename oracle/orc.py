@@ -182,7 +182,7 @@ class Oracle:
     def get(self, name, mode=COUPLED):
         m = self.mech
         N = self.N
-        shapes = {"R": (m.nv, N), "dtau": (N,), "omega": (m.nv, N), "dqs": (self.nsol(mode), N),
+        shapes = {"R": (m.nv, N), "dtau": (N,), "V": (N,), "omega": (m.nv, N), "dqs": (self.nsol(mode), N),
                   "dq": (self.nsol(mode), N), "T": (N,), "Tv": (N,), "p": (N,), "c": (N,),
                   "qw": (self.ni,), "dK": (N,), "dF": (N,), "dC": (N,), "JK": (m.nb, m.nb, N),
                   "JC": (m.ns, m.ns, N), "Jve": (m.nf, N), "DK": (m.nb, m.nb, N), "DF": (m.nf, m.nf, N),

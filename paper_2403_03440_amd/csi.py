@@ -1,0 +1,241 @@
+"""Thin Python binding of libcsi.so (include/csi.h): argument marshalling only.
+
+Device memory (the workspace) and the stream come from PyTorch; every step of
+the solver runs in the library's HIP kernels.  There is no fallback: if the
+library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsi.so")
+
+COUPLED, SPLIT = 0, 1
+FP64, MIXED = 0, 1
+CLOSURE, CC1, CC2 = 0, 1, 2
+JAC_EXACT, JAC_SURROGATE = 0, 1
+ERRORS = {-1: "CSI_ERR_ARG", -2: "CSI_ERR_STATE", -3: "CSI_ERR_HIP", -4: "CSI_ERR_NONFINITE",
+          -5: "CSI_ERR_SINGULAR", -6: "CSI_ERR_UNSUPPORTED"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_set_mechanism",
+            "csi_set_freestream", "csi_workspace_bytes", "csi_bind_workspace", "csi_set_state", "csi_get_state",
+            "csi_residual", "csi_implicit_op", "csi_consistency_correct", "csi_step", "csi_wall_heat_flux",
+            "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times"]
+PHASES = ["prim", "faces", "cell", "norms", "sweeps", "update"]
+
+
+class CsiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CsiMechanism(C.Structure):
+    _fields_ = [("ns", C.c_int), ("nr", C.c_int), ("two_temp", C.c_int),
+                ("M", _dp), ("theta_v", _dp), ("theta_r", _dp), ("sigma", _dp), ("g_el", _dp), ("h_form", _dp),
+                ("sc", _dp), ("lt_a", _dp), ("lt_b", _dp), ("kind", _ip), ("A", _dp), ("b", _dp), ("theta", _dp),
+                ("tctl", _ip), ("third", _ip), ("nu_f", _ip), ("nu_b", _ip), ("eff", _dp),
+                ("mu_ref", C.c_double), ("T_ref", C.c_double), ("mu_exp", C.c_double)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("mode", C.c_int), ("precision", C.c_int), ("kind", C.c_int), ("jac", C.c_int),
+                ("cfl", C.c_double), ("cfl_ramp", C.c_int), ("max_iter", C.c_int), ("tol", C.c_double),
+                ("check_every", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("it_conv", C.c_int), ("n_clipped", C.c_int),
+                ("bad_cell", C.c_int), ("r0", C.c_double), ("r_last", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libcsi.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
+                              "python paper_2403_03440_amd/build.py")
+        _lib = C.CDLL(LIB_PATH)
+        _lib.csi_last_error.restype = C.c_char_p
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+class Solver:
+    """One library context on cuda:`device` with its workspace tensor."""
+
+    def __init__(self, grid, mech, freestream, T_wall: float = 300.0, bc_mode: int = 0, device: int = 0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.device = device
+        self.dev = torch.device("cuda", device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.stream = st
+        self.ctx = C.c_void_p()
+        rc = self.L.csi_create(C.byref(self.ctx), device, C.c_void_p(st.cuda_stream))
+        if rc:
+            raise CsiError(rc, "csi_create")
+        x, y = grid
+        nj1, ni1 = x.shape
+        self.ni, self.nj = ni1 - 1, nj1 - 1
+        self.N = self.ni * self.nj
+        xa, xp = _d(x)
+        ya, yp = _d(y)
+        self._check(self.L.csi_set_grid(self.ctx, self.ni, self.nj, xp, yp, C.c_double(T_wall), bc_mode))
+        self.set_mechanism(mech)
+        self.set_freestream(*freestream)
+        nbytes = C.c_size_t(0)
+        self._check(self.L.csi_workspace_bytes(self.ctx, C.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.dev)
+        self._check(self.L.csi_bind_workspace(self.ctx, C.c_void_p(self.ws.data_ptr()), C.c_size_t(nbytes.value)))
+        self.last_mode = None
+
+    def __del__(self):
+        try:
+            self.L.csi_destroy(self.ctx)
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CsiError(rc, self.L.csi_last_error(self.ctx).decode())
+
+    def set_mechanism(self, m):
+        keep = []
+
+        def d(a):
+            arr, p = _d(a)
+            keep.append(arr)
+            return p
+
+        def i(a):
+            arr, p = _i(a)
+            keep.append(arr)
+            return p
+
+        nr = m.nr
+        s = CsiMechanism(m.ns, nr, int(m.two_temp), d(m.M), d(m.theta_v), d(m.theta_r), d(m.sigma), d(m.g_el),
+                         d(m.h_form), d(m.sc), d(m.lt_a), d(m.lt_b), i(m.kind),
+                         d(m.A if nr else [0.0]), d(m.b if nr else [0.0]), d(m.theta if nr else [0.0]),
+                         i(m.tctl if nr else [0]), i(m.third if nr else [0]),
+                         i(np.asarray(m.nu_f).ravel() if nr else [0]), i(np.asarray(m.nu_b).ravel() if nr else [0]),
+                         d(np.asarray(m.eff).ravel() if nr else [0.0]), m.mu_ref, m.T_ref, m.mu_exp)
+        self._check(self.L.csi_set_mechanism(self.ctx, C.byref(s)))
+        self.mech = m
+
+    def set_freestream(self, rho_s, u, v, T, Tv):
+        a, p = _d(rho_s)
+        self._check(self.L.csi_set_freestream(self.ctx, p, C.c_double(u), C.c_double(v), C.c_double(T),
+                                              C.c_double(Tv)))
+
+    # ------------------------------------------------------------- state
+    def set_state(self, q):
+        if isinstance(q, np.ndarray):
+            a, p = _d(q)
+            self._check(self.L.csi_set_state(self.ctx, p, 0))
+        else:
+            t = q.to(device=self.dev, dtype=self.torch.float64).contiguous()
+            self._check(self.L.csi_set_state(self.ctx, C.c_void_p(t.data_ptr()), 1))
+
+    def get_state(self):
+        q = np.zeros((self.mech.nv, self.N))
+        self._check(self.L.csi_get_state(self.ctx, q.ctypes.data_as(_dp), 0))
+        return q
+
+    def get_state_device(self):
+        t = self.torch.empty((self.mech.nv, self.N), dtype=self.torch.float64, device=self.dev)
+        self._check(self.L.csi_get_state(self.ctx, C.c_void_p(t.data_ptr()), 1))
+        return t
+
+    # --------------------------------------------------------- algorithm
+    def residual(self, cfl):
+        n = np.zeros(2)
+        self._check(self.L.csi_residual(self.ctx, C.c_double(cfl), n.ctypes.data_as(_dp)))
+        return n
+
+    def implicit_op(self, mode, precision=FP64, jac=JAC_EXACT):
+        self._check(self.L.csi_implicit_op(self.ctx, mode, precision, jac))
+        self.last_mode = mode
+
+    def consistency_correct(self, kind):
+        self._check(self.L.csi_consistency_correct(self.ctx, kind))
+
+    def step(self, mode, kind, cfl, max_iter, precision=FP64, jac=JAC_EXACT, cfl_ramp=0, tol=0.0, check_every=50):
+        p = StepParams(mode, precision, kind, jac, cfl, cfl_ramp, max_iter, tol, check_every)
+        s = StepStats()
+        self._check(self.L.csi_step(self.ctx, C.byref(p), C.byref(s)))
+        return {k: getattr(s, k) for k, _ in StepStats._fields_}
+
+    def norm_history(self, n):
+        h = np.zeros((n, 2))
+        self._check(self.L.csi_norm_history(self.ctx, n, h.ctypes.data_as(_dp)))
+        return h
+
+    def wall_heat_flux(self):
+        qw = np.zeros(self.ni)
+        qs = C.c_double(0)
+        self._check(self.L.csi_wall_heat_flux(self.ctx, qw.ctypes.data_as(_dp), C.byref(qs)))
+        return qw, qs.value
+
+    def nsol(self, mode):
+        return self.mech.nb if mode == COUPLED else self.mech.nf + self.mech.ns
+
+    def get(self, name, mode: Optional[int] = None):
+        m = self.mech
+        N = self.N
+        mode = self.last_mode if mode is None else mode
+        shapes = {"R": (m.nv, N), "dtau": (N,), "src": (m.nv, N), "qw": (self.ni,), "T": (N,), "Tv": (N,),
+                  "p": (N,), "c": (N,)}
+        if name in ("b", "dqs", "dq"):
+            shape = (self.nsol(mode), N)
+        elif name == "Dinv":
+            shape = (m.nb * m.nb, N) if mode == COUPLED else (6 + m.ns * m.ns, N)
+        else:
+            shape = shapes[name]
+        out = np.zeros(shape)
+        self._check(self.L.csi_get_array(self.ctx, name.encode(), out.ctypes.data_as(_dp), C.c_size_t(out.size)))
+        return out
+
+    def initial_state(self, rho_s, u, v, T, Tv):
+        """Conservative variables from primitives with the library's thermodynamics."""
+        rho_s = np.atleast_2d(rho_s)
+        n = rho_s.shape[1]
+        q = np.zeros((self.mech.nv, n))
+        args = [_d(a) for a in (rho_s, u, v, T, Tv)]
+        self._check(self.L.csi_prim_to_cons(self.ctx, n, *[p for _, p in args], q.ctypes.data_as(_dp)))
+        return q
+
+    def set_timing(self, on=True):
+        self._check(self.L.csi_set_timing(self.ctx, int(on)))
+
+    def phase_times(self, reset=False):
+        ms = np.zeros(7)
+        self._check(self.L.csi_phase_times(self.ctx, ms.ctypes.data_as(_dp), int(reset)))
+        n = max(ms[6], 1.0)
+        return {k: {"ms": float(ms[i]), "ms_per_iter": float(ms[i] / n)} for i, k in enumerate(PHASES)}
+
+    def synchronize(self):
+        self.torch.cuda.synchronize(self.dev)

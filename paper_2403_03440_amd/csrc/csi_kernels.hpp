@@ -1,0 +1,600 @@
+// HIP kernels of one pseudo-time iteration of the coupled / component-split
+// implicit solver for gfx950.  Data are structure-of-arrays in HBM, index
+// var*N + j*ni + i (i fastest) so that consecutive lanes touch consecutive
+// doubles.  Primitive records carry one ghost layer ((ni+2) x (nj+2)).
+#pragma once
+#include "csi_phys.hpp"
+
+namespace csi {
+
+// ------------------------------------------------------------ workspace view
+struct Geo {
+  int ni, nj, N, NP, bc_mode;
+  double Tw;
+  const double *V, *xc, *yc, *xn, *yn;
+  const double *fi_nx, *fi_ny, *fi_S;  // i-faces, index j*(ni+1)+I, normal towards +i
+  const double *fj_nx, *fj_ny, *fj_S;  // j-faces, index J*ni+i, normal towards +j
+};
+
+// primitive record fields
+enum {
+  F_RHO = 0, F_U, F_V, F_T, F_TV, F_P, F_C, F_H, F_EVE, F_RE, F_MU, F_K, F_KVE, F_NUF, F_NUC, F_NUK,
+  F_PE, F_PV, F_Y0
+};
+template <int NS> struct PF {
+  static constexpr int Y = F_Y0, HS = F_Y0 + NS, EVS = F_Y0 + 2 * NS, PR = F_Y0 + 3 * NS, N = F_Y0 + 4 * NS;
+};
+// face radius fields
+enum { R_LAM = 0, R_UABS, R_LVF, R_LVC, R_LVK, R_N };
+
+__device__ __forceinline__ int padc(const Geo &g, int i, int j) { return (j + 1) * (g.ni + 2) + (i + 1); }
+
+// --------------------------------------------------------------- primitives
+// One thread per padded cell: interior cells from Q; ghosts by the boundary
+// conditions (wall mirror, far-field free stream, zero-gradient outflow) or
+// all free stream (bc_mode 1).
+template <int NS, int NT>
+__global__ void __launch_bounds__(256) k_prim(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
+                                              const double *__restrict__ qfs, double *__restrict__ prim,
+                                              int *__restrict__ bad, const int *__restrict__ done) {
+  using D = Dims<NS, NT>;
+  if (done && *done) return;
+  int pc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pc >= g.NP) return;
+  const Mech &m = *mech;
+  int i = pc % (g.ni + 2) - 1, j = pc / (g.ni + 2) - 1;
+  bool interior = i >= 0 && i < g.ni && j >= 0 && j < g.nj;
+  int si = i < 0 ? 0 : (i >= g.ni ? g.ni - 1 : i);
+  bool use_fs = false, mirror = false;
+  if (!interior) {
+    if (g.bc_mode == 1) use_fs = true;
+    else if (j >= g.nj) use_fs = true;
+    else if (j < 0) mirror = true;
+  }
+  double q[D::nv];
+  if (use_fs) {
+#pragma unroll
+    for (int k = 0; k < D::nv; ++k) q[k] = qfs[k];
+  } else {
+    int sj = j < 0 ? 0 : j;
+    int c = sj * g.ni + si;
+#pragma unroll
+    for (int k = 0; k < D::nv; ++k) q[k] = Q[size_t(k) * g.N + c];
+  }
+  Prim<NS, NT> P;
+  bool ok = prim_from_q<NS, NT>(m, q, P);
+  if (!ok) {
+    if (interior && bad) atomicMin(bad, j * g.ni + i);
+    return;
+  }
+  Transport t;
+  transport<NS, NT>(m, P, t);
+  if (mirror) {
+    int f = si;  // wall face (si, 0)
+    double nx = g.fj_nx[f], ny = g.fj_ny[f];
+    double un = P.u * nx + P.v * ny;
+    P.u = P.u - 2.0 * un * nx;
+    P.v = P.v - 2.0 * un * ny;
+  }
+  const size_t NP = g.NP;
+  double *o = prim + pc;
+  o[F_RHO * NP] = P.rho; o[F_U * NP] = P.u; o[F_V * NP] = P.v; o[F_T * NP] = P.T; o[F_TV * NP] = P.Tv;
+  o[F_P * NP] = P.p; o[F_C * NP] = P.c; o[F_H * NP] = P.H; o[F_EVE * NP] = P.eve; o[F_RE * NP] = P.rE;
+  o[F_MU * NP] = t.mu; o[F_K * NP] = t.k; o[F_KVE * NP] = t.kve; o[F_NUF * NP] = t.nuF; o[F_NUC * NP] = t.nuC;
+  o[F_NUK * NP] = t.nuK; o[F_PE * NP] = P.pE; o[F_PV * NP] = P.pv;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    o[(PF<NS>::Y + s) * NP] = P.Y[s];
+    o[(PF<NS>::HS + s) * NP] = m.cvtr[s] * P.T + eve_s(m, s, P.Tv) + m.hf[s] + m.R[s] * (m.kind[s] == ELECTRON ? P.Tv : P.T);
+    o[(PF<NS>::EVS + s) * NP] = eve_s(m, s, P.Tv);
+    o[(PF<NS>::PR + s) * NP] = P.pr[s];
+  }
+}
+
+// ----------------------------------------------------------------- faces
+template <int NS> struct FaceState {
+  double rho, u, v, p, c, H, eve, rE, Y[NS];
+};
+template <int NS>
+__device__ __forceinline__ void load_face_state(const double *prim, size_t NP, int pc, FaceState<NS> &s) {
+  s.rho = prim[F_RHO * NP + pc]; s.u = prim[F_U * NP + pc]; s.v = prim[F_V * NP + pc];
+  s.p = prim[F_P * NP + pc]; s.c = prim[F_C * NP + pc]; s.H = prim[F_H * NP + pc];
+  s.eve = prim[F_EVE * NP + pc]; s.rE = prim[F_RE * NP + pc];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s.Y[k] = prim[(PF<NS>::Y + k) * NP + pc];
+}
+
+// HLLE (Davis bounds) for mass, momentum and total energy; species and e_ve
+// carried by the mixture mass flux with upwind mass fraction / e_ve.
+template <int NS, int NT>
+__device__ __forceinline__ void hlle_flux(const FaceState<NS> &L, const FaceState<NS> &R, double nx, double ny,
+                                          double *F) {
+  double unL = L.u * nx + L.v * ny, unR = R.u * nx + R.v * ny;
+  double SL = fmin(unL - L.c, unR - R.c), SR = fmax(unL + L.c, unR + R.c);
+  double sl = fmin(SL, 0.0), sr = fmax(SR, 0.0);
+  double id = 1.0 / (sr - sl);
+  auto hll = [&](double fl, double fr, double ql, double qr) { return (sr * fl - sl * fr + sr * sl * (qr - ql)) * id; };
+  double fm = hll(L.rho * unL, R.rho * unR, L.rho, R.rho);
+  const FaceState<NS> &U = fm >= 0.0 ? L : R;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) F[s] = fm * U.Y[s];
+  double mxL = L.rho * L.u, myL = L.rho * L.v, mxR = R.rho * R.u, myR = R.rho * R.v;
+  F[NS] = hll(mxL * unL + L.p * nx, mxR * unR + R.p * nx, mxL, mxR);
+  F[NS + 1] = hll(myL * unL + L.p * ny, myR * unR + R.p * ny, myL, myR);
+  F[NS + 2] = hll((L.rE + L.p) * unL, (R.rE + R.p) * unR, L.rE, R.rE);
+  if (NT == 2) F[NS + 3] = fm * U.eve;
+}
+
+// gradient from the two diagonals of the diamond: d1.g = D1, d2.g = D2
+__device__ __forceinline__ void diamond_grad(double d1x, double d1y, double d2x, double d2y, double D1, double D2,
+                                             double &gx, double &gy) {
+  double det = d1x * d2y - d1y * d2x;
+  gx = (D1 * d2y - D2 * d1y) / det;
+  gy = (D2 * d1x - D1 * d2x) / det;
+}
+
+// value of variable var (0 u, 1 v, 2 T, 3 Tv, 4+s Y_s) at grid node (I, J)
+template <int NS>
+__device__ __forceinline__ double node_value(const Geo &g, const double *prim, int I, int J, int var) {
+  const size_t NP = g.NP;
+  int fld = var == 0 ? F_U : var == 1 ? F_V : var == 2 ? F_T : var == 3 ? F_TV : PF<NS>::Y + var - 4;
+  if (g.bc_mode == 0 && J == 0) {
+    if (var <= 1) return 0.0;
+    if (var <= 3) return g.Tw;
+    return 0.5 * (prim[fld * NP + padc(g, I - 1, 0)] + prim[fld * NP + padc(g, I, 0)]);
+  }
+  return 0.25 * (prim[fld * NP + padc(g, I - 1, J - 1)] + prim[fld * NP + padc(g, I, J - 1)] +
+                 prim[fld * NP + padc(g, I - 1, J)] + prim[fld * NP + padc(g, I, J)]);
+}
+
+template <int NS, int NT>
+__device__ __forceinline__ double cellvar(const double *prim, size_t NP, int pc, int var) {
+  int fld = var == 0 ? F_U : var == 1 ? F_V : var == 2 ? F_T : var == 3 ? F_TV : PF<NS>::Y + var - 4;
+  return prim[fld * NP + pc];
+}
+
+// Viscous flux F_vis.n at an interior face (paper Section 2.1 constitutive
+// laws; diffusion fluxes corrected to sum to zero)
+template <int NS, int NT>
+__device__ __forceinline__ void viscous_interior(const Geo &g, const Mech &m, const double *prim, int pL, int pR,
+                                                 double xL, double yL, double xR, double yR, int IA, int JA, int IB,
+                                                 int JB, double nx, double ny, double *F) {
+  const size_t NP = g.NP;
+  double d1x = xR - xL, d1y = yR - yL;
+  int nA = JA * (g.ni + 1) + IA, nB = JB * (g.ni + 1) + IB;
+  double d2x = g.xn[nB] - g.xn[nA], d2y = g.yn[nB] - g.yn[nA];
+  double gr[4 + NS][2];
+#pragma unroll
+  for (int var = 0; var < 4 + NS; ++var) {
+    double D1 = cellvar<NS, NT>(prim, NP, pR, var) - cellvar<NS, NT>(prim, NP, pL, var);
+    double D2 = node_value<NS>(g, prim, IB, JB, var) - node_value<NS>(g, prim, IA, JA, var);
+    diamond_grad(d1x, d1y, d2x, d2y, D1, D2, gr[var][0], gr[var][1]);
+  }
+  auto avg = [&](int fld) { return 0.5 * (prim[fld * NP + pL] + prim[fld * NP + pR]); };
+  double mu = avg(F_MU), k = avg(F_K), kve = avg(F_KVE), u = avg(F_U), v = avg(F_V);
+  double div = gr[0][0] + gr[1][1];
+  double txx = mu * (2.0 * gr[0][0] - 2.0 / 3.0 * div);
+  double tyy = mu * (2.0 * gr[1][1] - 2.0 / 3.0 * div);
+  double txy = mu * (gr[0][1] + gr[1][0]);
+  double muL = prim[F_MU * NP + pL], muR = prim[F_MU * NP + pR];
+  double Jcx = 0.0, Jcy = 0.0, rD[NS], Yf[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    rD[s] = 0.5 * (muL * m.iSc[s] + muR * m.iSc[s]);
+    Yf[s] = avg(PF<NS>::Y + s);
+    Jcx += rD[s] * gr[4 + s][0];
+    Jcy += rD[s] * gr[4 + s][1];
+  }
+  double hJ = 0.0, eJ = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double jx = -rD[s] * gr[4 + s][0] + Yf[s] * Jcx;
+    double jy = -rD[s] * gr[4 + s][1] + Yf[s] * Jcy;
+    double jn = jx * nx + jy * ny;
+    F[s] = jn;
+    hJ += avg(PF<NS>::HS + s) * jn;
+    eJ += avg(PF<NS>::EVS + s) * jn;
+  }
+  double tnx = txx * nx + txy * ny, tny = txy * nx + tyy * ny;
+  double qtr = -k * (gr[2][0] * nx + gr[2][1] * ny);
+  double qve = -kve * (gr[3][0] * nx + gr[3][1] * ny);
+  F[NS] = -tnx;
+  F[NS + 1] = -tny;
+  F[NS + 2] = -(u * tnx + v * tny) + qtr + qve + hJ;
+  if (NT == 2) F[NS + 3] = qve + eJ;
+}
+
+template <int NS, int NT>
+__device__ __forceinline__ void radii(const Geo &g, const double *prim, int pL, int pR, bool interior, int pIn,
+                                      double VL, double VR, double Vin, double nx, double ny, double S, double *rad) {
+  const size_t NP = g.NP;
+  double U = 0.5 * ((prim[F_U * NP + pL] + prim[F_U * NP + pR]) * nx + (prim[F_V * NP + pL] + prim[F_V * NP + pR]) * ny);
+  rad[R_UABS] = fabs(U);
+  rad[R_LAM] = fabs(U) + 0.5 * (prim[F_C * NP + pL] + prim[F_C * NP + pR]);
+  double nF, nC, nK, Vf;
+  if (interior) {
+    nF = 0.5 * (prim[F_NUF * NP + pL] + prim[F_NUF * NP + pR]);
+    nC = 0.5 * (prim[F_NUC * NP + pL] + prim[F_NUC * NP + pR]);
+    nK = 0.5 * (prim[F_NUK * NP + pL] + prim[F_NUK * NP + pR]);
+    Vf = 0.5 * (VL + VR);
+  } else {
+    nF = prim[F_NUF * NP + pIn];
+    nC = prim[F_NUC * NP + pIn];
+    nK = prim[F_NUK * NP + pIn];
+    Vf = Vin;
+  }
+  rad[R_LVF] = nF * S / Vf;
+  rad[R_LVC] = nC * S / Vf;
+  rad[R_LVK] = nK * S / Vf;
+}
+
+// i-faces: (I, j), I in [0, ni], j in [0, nj)
+template <int NS, int NT>
+__global__ void __launch_bounds__(256) k_face_i(Geo g, const Mech *__restrict__ mech, const double *__restrict__ prim,
+                                                double *__restrict__ Fi, double *__restrict__ Ri,
+                                                const int *__restrict__ done) {
+  using D = Dims<NS, NT>;
+  if (done && *done) return;
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  int nfc = (g.ni + 1) * g.nj;
+  if (f >= nfc) return;
+  int I = f % (g.ni + 1), j = f / (g.ni + 1);
+  const size_t NP = g.NP;
+  int pL = padc(g, I - 1, j), pR = padc(g, I, j);
+  double nx = g.fi_nx[f], ny = g.fi_ny[f], S = g.fi_S[f];
+  FaceState<NS> L, R;
+  load_face_state<NS>(prim, NP, pL, L);
+  load_face_state<NS>(prim, NP, pR, R);
+  double F[D::nv];
+  hlle_flux<NS, NT>(L, R, nx, ny, F);
+  bool interior = I > 0 && I < g.ni;
+  double rad[R_N];
+  int cin = j * g.ni + (I == 0 ? 0 : g.ni - 1);
+  radii<NS, NT>(g, prim, pL, pR, interior, padc(g, I == 0 ? 0 : g.ni - 1, j), interior ? g.V[j * g.ni + I - 1] : 0.0,
+                interior ? g.V[j * g.ni + I] : 0.0, g.V[cin], nx, ny, S, rad);
+  if (interior) {
+    double Fv[D::nv];
+    int cL = j * g.ni + I - 1, cR = j * g.ni + I;
+    viscous_interior<NS, NT>(g, *mech, prim, pL, pR, g.xc[cL], g.yc[cL], g.xc[cR], g.yc[cR], I, j, I, j + 1, nx, ny, Fv);
+#pragma unroll
+    for (int k = 0; k < D::nv; ++k) F[k] += Fv[k];
+  }
+#pragma unroll
+  for (int k = 0; k < D::nv; ++k) Fi[size_t(k) * nfc + f] = F[k];
+#pragma unroll
+  for (int k = 0; k < R_N; ++k) Ri[size_t(k) * nfc + f] = rad[k];
+}
+
+// j-faces: (i, J), i in [0, ni), J in [0, nj]; J = 0 is the wall in bc_mode 0
+template <int NS, int NT>
+__global__ void __launch_bounds__(256) k_face_j(Geo g, const Mech *__restrict__ mech, const double *__restrict__ prim,
+                                                double *__restrict__ Fj, double *__restrict__ Rj,
+                                                double *__restrict__ qw, const int *__restrict__ done) {
+  using D = Dims<NS, NT>;
+  if (done && *done) return;
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  int nfc = g.ni * (g.nj + 1);
+  if (f >= nfc) return;
+  const Mech &m = *mech;
+  int i = f % g.ni, J = f / g.ni;
+  const size_t NP = g.NP;
+  int pL = padc(g, i, J - 1), pR = padc(g, i, J);
+  double nx = g.fj_nx[f], ny = g.fj_ny[f], S = g.fj_S[f];
+  FaceState<NS> L, R;
+  load_face_state<NS>(prim, NP, pL, L);
+  load_face_state<NS>(prim, NP, pR, R);
+  double F[D::nv];
+  hlle_flux<NS, NT>(L, R, nx, ny, F);
+  bool interior = J > 0 && J < g.nj;
+  double rad[R_N];
+  int cin = (J == 0 ? 0 : g.nj - 1) * g.ni + i;
+  radii<NS, NT>(g, prim, pL, pR, interior, padc(g, i, J == 0 ? 0 : g.nj - 1), interior ? g.V[(J - 1) * g.ni + i] : 0.0,
+                interior ? g.V[J * g.ni + i] : 0.0, g.V[cin], nx, ny, S, rad);
+  if (interior) {
+    double Fv[D::nv];
+    int cL = (J - 1) * g.ni + i, cR = J * g.ni + i;
+    viscous_interior<NS, NT>(g, m, prim, pL, pR, g.xc[cL], g.yc[cL], g.xc[cR], g.yc[cR], i, J, i + 1, J, nx, ny, Fv);
+#pragma unroll
+    for (int k = 0; k < D::nv; ++k) F[k] += Fv[k];
+  } else if (J == 0 && g.bc_mode == 0) {
+    // isothermal no-slip non-catalytic wall: wall values at the face, normal
+    // gradient between the face centre and the first cell centre
+    int c0 = i;
+    double muw = m.mu_ref * exp(m.mu_exp * log(g.Tw / m.T_ref));
+    double ktr = 0.0, kint = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double Y = R.Y[s];
+      ktr += Y * m.ck[s];
+      kint += Y * cvve_s(m, s, g.Tw);
+    }
+    double kw = NT == 2 ? muw * ktr : muw * (ktr + kint);
+    double kvw = NT == 2 ? muw * kint : 0.0;
+    int nA = i, nB = i + 1;
+    double xf = 0.5 * (g.xn[nA] + g.xn[nB]), yf = 0.5 * (g.yn[nA] + g.yn[nB]);
+    double d1x = g.xc[c0] - xf, d1y = g.yc[c0] - yf;
+    double d2x = g.xn[nB] - g.xn[nA], d2y = g.yn[nB] - g.yn[nA];
+    double gu[2], gv[2], gT[2], gTv[2];
+    diamond_grad(d1x, d1y, d2x, d2y, prim[F_U * NP + pR], 0.0, gu[0], gu[1]);
+    diamond_grad(d1x, d1y, d2x, d2y, prim[F_V * NP + pR], 0.0, gv[0], gv[1]);
+    diamond_grad(d1x, d1y, d2x, d2y, prim[F_T * NP + pR] - g.Tw, 0.0, gT[0], gT[1]);
+    diamond_grad(d1x, d1y, d2x, d2y, prim[F_TV * NP + pR] - g.Tw, 0.0, gTv[0], gTv[1]);
+    double div = gu[0] + gv[1];
+    double txx = muw * (2.0 * gu[0] - 2.0 / 3.0 * div);
+    double tyy = muw * (2.0 * gv[1] - 2.0 / 3.0 * div);
+    double txy = muw * (gu[1] + gv[0]);
+    double tnx = txx * nx + txy * ny, tny = txy * nx + tyy * ny;
+    double qtr = -kw * (gT[0] * nx + gT[1] * ny);
+    double qve = -kvw * (gTv[0] * nx + gTv[1] * ny);
+    F[NS] += -tnx;
+    F[NS + 1] += -tny;
+    F[NS + 2] += qtr + qve;
+    if (NT == 2) F[NS + 3] += qve;
+    qw[i] = -(qtr + qve);
+  }
+#pragma unroll
+  for (int k = 0; k < D::nv; ++k) Fj[size_t(k) * nfc + f] = F[k];
+#pragma unroll
+  for (int k = 0; k < R_N; ++k) Rj[size_t(k) * nfc + f] = rad[k];
+}
+
+// ------------------------------------------------------- dense inversion
+// In-register Gauss-Jordan inversion with partial pivoting (largest |a|,
+// lowest row on ties).  Returns false on a zero pivot.
+template <int N>
+__device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) inv[r][c] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int p = k;
+    double best = fabs(a[k][k]);
+#pragma unroll
+    for (int r = k + 1; r < N; ++r)
+      if (fabs(a[r][k]) > best) { best = fabs(a[r][k]); p = r; }
+    if (best == 0.0) return false;
+    if (p != k) {
+#pragma unroll
+      for (int r = k + 1; r < N; ++r) {
+        if (r == p) {
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            double t = a[k][c]; a[k][c] = a[r][c]; a[r][c] = t;
+            t = inv[k][c]; inv[k][c] = inv[r][c]; inv[r][c] = t;
+          }
+        }
+      }
+    }
+    double ip = 1.0 / a[k][k];
+#pragma unroll
+    for (int c = 0; c < N; ++c) { a[k][c] *= ip; inv[k][c] *= ip; }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      if (r == k) continue;
+      double l = a[r][k];
+#pragma unroll
+      for (int c = 0; c < N; ++c) { a[r][c] -= l * a[k][c]; inv[r][c] -= l * inv[k][c]; }
+    }
+  }
+  return true;
+}
+
+// ----------------------------------------------------------- cell kernel
+// Residual R = sum_f F_f S_f - V S(Q), local time step, norms partials,
+// chemistry and its Jacobian, the diagonal blocks (paper Section 2.2: I_m and
+// the split-radius diagonals of Section 2.3) and their inverses, and the RHS.
+// mode 0: coupled (nb x nb block in z = rho, momenta, energies, rho_1..rho_{ns-1})
+// mode 1: split (flow block in closed form, ns x ns species block)
+struct CellOut {
+  double *R, *dtau, *part;     // part: per-block norm partials [2][nblocks]
+  void *Dinv;                  // coupled: [nb*nb][N]; split: DF [6][N] then DC [ns*ns][N]
+  void *b;                     // RHS [nsol][N]
+  double *src;                 // optional source vector [nv][N] (debug)
+  int *bad;
+};
+
+template <int NS, int NT, typename RT>
+__global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
+                                              const double *__restrict__ prim, const double *__restrict__ Fi,
+                                              const double *__restrict__ Fj, const double *__restrict__ Ri,
+                                              const double *__restrict__ Rj, double cfl, int mode, int flags,
+                                              CellOut out, const int *__restrict__ done) {
+  using D = Dims<NS, NT>;
+  constexpr int NV = D::nv, NB = D::nb, NF = D::nf;
+  if (done && *done) return;
+  __shared__ double red[2][256];
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  double nr2 = 0.0, ne2 = 0.0;
+  if (p < g.N) {
+    const Mech &m = *mech;
+    const size_t NP = g.NP;
+    int i = p % g.ni, j = p / g.ni;
+    int pc = padc(g, i, j);
+    int nfi = (g.ni + 1) * g.nj, nfj = g.ni * (g.nj + 1);
+    int fW = j * (g.ni + 1) + i, fE = fW + 1, fS = j * g.ni + i, fN = fS + g.ni;
+    double SW = g.fi_S[fW], SE = g.fi_S[fE], SS = g.fj_S[fS], SN = g.fj_S[fN];
+    double Vp = g.V[p];
+    double q[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) q[k] = Q[size_t(k) * g.N + p];
+    double rs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) rs[s] = q[s];
+    double T = prim[F_T * NP + pc], Tv = prim[F_TV * NP + pc], pp = prim[F_P * NP + pc];
+    Chem<NS, NT> C;
+    const bool do_res = flags & 1, do_diag = flags & 2;
+    if (do_diag) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
+    else chemistry<NS, NT, false>(m, rs, T, Tv, pp, C);
+    double R[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      if (do_res) {
+        double sv = k < NS ? C.w[k] : (NT == 2 && k == NS + 3 ? C.wv : 0.0);
+        R[k] = Fi[size_t(k) * nfi + fE] * SE - Fi[size_t(k) * nfi + fW] * SW + Fj[size_t(k) * nfj + fN] * SN -
+               Fj[size_t(k) * nfj + fS] * SS - Vp * sv;
+        out.R[size_t(k) * g.N + p] = R[k];
+        if (out.src) out.src[size_t(k) * g.N + p] = sv;
+      } else {
+        R[k] = out.R[size_t(k) * g.N + p];
+      }
+    }
+    double slam = Ri[size_t(R_LAM) * nfi + fW] * SW + Ri[size_t(R_LAM) * nfi + fE] * SE +
+                  Rj[size_t(R_LAM) * nfj + fS] * SS + Rj[size_t(R_LAM) * nfj + fN] * SN;
+    double sU = Ri[size_t(R_UABS) * nfi + fW] * SW + Ri[size_t(R_UABS) * nfi + fE] * SE +
+                Rj[size_t(R_UABS) * nfj + fS] * SS + Rj[size_t(R_UABS) * nfj + fN] * SN;
+    double svF = Ri[size_t(R_LVF) * nfi + fW] * SW + Ri[size_t(R_LVF) * nfi + fE] * SE +
+                 Rj[size_t(R_LVF) * nfj + fS] * SS + Rj[size_t(R_LVF) * nfj + fN] * SN;
+    double svC = Ri[size_t(R_LVC) * nfi + fW] * SW + Ri[size_t(R_LVC) * nfi + fE] * SE +
+                 Rj[size_t(R_LVC) * nfj + fS] * SS + Rj[size_t(R_LVC) * nfj + fN] * SN;
+    double svK = Ri[size_t(R_LVK) * nfi + fW] * SW + Ri[size_t(R_LVK) * nfi + fE] * SE +
+                 Rj[size_t(R_LVK) * nfj + fS] * SS + Rj[size_t(R_LVK) * nfj + fN] * SN;
+    double dt;
+    if (do_res) {
+      dt = cfl * Vp / (0.5 * (slam + svK));
+      out.dtau[p] = dt;
+      double rr = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) rr += R[s];
+      rr /= Vp;
+      double re_ = R[NS + 2] / Vp;
+      nr2 = rr * rr;
+      ne2 = re_ * re_;
+    } else {
+      dt = out.dtau[p];
+    }
+    if (!do_diag) goto reduce;
+    {
+    // temperature derivatives w.r.t. stored variables (recomputed from the state)
+    Prim<NS, NT> P;
+    prim_from_q<NS, NT>(m, q, P);
+    double Vdt = Vp / dt;
+    RT *bb = reinterpret_cast<RT *>(out.b);
+    if (mode == 0) {
+      // coupled: dS_z/dz, z = (rho, m_x, m_y, rhoE, [rhoe_ve], rho_0..rho_{ns-2})
+      // storage derivative of omega_s: dw/dq_j = dw_dr + dw_dT dT/dq_j + dw_dTv dTv/dq_j
+      double dK = Vdt + 0.5 * slam + svK;
+      double A[NB][NB];
+      {
+        double Jz[NB][NB];
+        coupled_source_jacobian<NS, NT>(P, C, Jz);
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) A[r][c] = (r == c ? dK : 0.0) - Vp * Jz[r][c];
+      }
+      double Ai[NB][NB];
+      bool ok = invert<NB>(A, Ai);
+      if (!ok && out.bad) atomicMin(out.bad, p);
+      RT *Di = reinterpret_cast<RT *>(out.Dinv);
+#pragma unroll
+      for (int r = 0; r < NB; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) Di[size_t(r * NB + c) * g.N + p] = RT(Ai[r][c]);
+      double rsum = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) rsum += R[s];
+      bb[size_t(0) * g.N + p] = RT(-rsum);
+      bb[size_t(1) * g.N + p] = RT(-R[NS]);
+      bb[size_t(2) * g.N + p] = RT(-R[NS + 1]);
+      bb[size_t(3) * g.N + p] = RT(-R[NS + 2]);
+      if (NT == 2) bb[size_t(4) * g.N + p] = RT(-R[NS + 3]);
+#pragma unroll
+      for (int s = 0; s < NS - 1; ++s) bb[size_t(NF + s) * g.N + p] = RT(-R[s]);
+    } else {
+      double dF = Vdt + 0.5 * slam + svF;
+      double dC = Vdt + 0.5 * sU + svC;
+      RT *DF = reinterpret_cast<RT *>(out.Dinv);
+      RT *DC = DF + size_t(6) * g.N;
+      // flow block: scalar rows, plus the rho e_ve row -V d omega_ve/dQ_F (frozen Y)
+      double df6[6];
+      df6[0] = 1.0 / dF;
+      for (int k = 1; k < 6; ++k) df6[k] = 0.0;
+      if (NT == 2) {
+        double dwv[5];
+        flow_source_row<NS, NT>(P, C, dwv);
+        // x4 = (r4 + V sum_{j<4} dwv_j x_j) / (dF - V dwv_4)
+        for (int k = 0; k < 4; ++k) df6[1 + k] = Vp * dwv[k];
+        double piv = dF - Vp * dwv[4];
+        if (piv == 0.0 && out.bad) atomicMin(out.bad, p);
+        df6[5] = 1.0 / piv;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) DF[size_t(k) * g.N + p] = RT(df6[k]);
+      double A[NS][NS], Ai[NS][NS];
+#pragma unroll
+      for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) A[r][c] = (r == c ? dC : 0.0) - Vp * C.dw_dr[r][c];
+      bool ok = invert<NS>(A, Ai);
+      if (!ok && out.bad) atomicMin(out.bad, p);
+#pragma unroll
+      for (int r = 0; r < NS; ++r)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) DC[size_t(r * NS + c) * g.N + p] = RT(Ai[r][c]);
+      double rsum = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) rsum += R[s];
+      bb[size_t(0) * g.N + p] = RT(-rsum);
+      bb[size_t(1) * g.N + p] = RT(-R[NS]);
+      bb[size_t(2) * g.N + p] = RT(-R[NS + 1]);
+      bb[size_t(3) * g.N + p] = RT(-R[NS + 2]);
+      if (NT == 2) bb[size_t(4) * g.N + p] = RT(-R[NS + 3]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bb[size_t(NF + s) * g.N + p] = RT(-R[s]);
+    }
+    }
+  }
+reduce:
+  if (!(flags & 1)) return;
+  // fixed-order block reduction of the norm partials
+  red[0][threadIdx.x] = nr2;
+  red[1][threadIdx.x] = ne2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out.part[blockIdx.x] = red[0][0];
+    out.part[gridDim.x + blockIdx.x] = red[1][0];
+  }
+}
+
+// Final fixed-order reduction of the norm partials (one block); records the
+// history and sets the stop flag once r/r0 <= tol.
+template <int NS>
+__global__ void __launch_bounds__(256) k_norms(const double *__restrict__ part, int nblk, double *__restrict__ norms,
+                                               double *__restrict__ hist, int it, int hist_max, double *__restrict__ r0,
+                                               double tol, int *__restrict__ done, int *__restrict__ it_done) {
+  if (done && *done) return;
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 256) { a += part[k]; b += part[nblk + k]; }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double nr = sqrt(red[0][0]), ne = sqrt(red[1][0]);
+    norms[0] = nr;
+    norms[1] = ne;
+    if (hist && it < hist_max) { hist[2 * it] = nr; hist[2 * it + 1] = ne; }
+    if (r0) {
+      if (it == 0 || *r0 == 0.0) *r0 = nr;
+      if (done && tol > 0.0 && nr <= tol * (*r0)) { *done = 1; if (it_done) *it_done = it; }
+    }
+  }
+}
+
+}  // namespace csi

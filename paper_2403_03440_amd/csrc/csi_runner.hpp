@@ -1,0 +1,118 @@
+// Launch sequences of one pseudo-time iteration, templated on the species
+// count and the temperature model; instantiated per species count in
+// csi_inst.hip and dispatched through the IRunner interface.
+#pragma once
+#include "csi_sweep.hpp"
+
+namespace csi {
+
+// device pointers inside the caller-owned workspace
+struct WS {
+  Mech *mech;
+  double *V, *xc, *yc, *xn, *yn, *fi_nx, *fi_ny, *fi_S, *fj_nx, *fj_ny, *fj_S;
+  double *qfs, *Q, *prim, *Fi, *Fj, *Ri, *Rj, *R, *dtau, *src, *qw, *part, *norms, *r0, *hist;
+  void *b, *dqs, *dq, *Dinv;
+  int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
+  int nblk_cell, hist_max;
+};
+enum { FL_BAD = 0, FL_DONE = 1, FL_ITDONE = 2, FL_CLIP = 3, FL_SING = 4, FL_N = 8 };
+
+class IRunner {
+ public:
+  virtual ~IRunner() {}
+  virtual int nprim() const = 0;
+  virtual hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
+  virtual hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
+  virtual hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
+                          bool stoppable) = 0;
+  virtual hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable) = 0;
+  virtual hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable) = 0;
+  virtual hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind,
+                            bool stoppable) = 0;
+  virtual hipError_t q_from_prim_host(const Mech &m, const double *rs, double u, double v, double T, double Tv,
+                                      double *q) = 0;
+};
+
+IRunner *make_runner(int ns, int nt);
+
+inline int nblocks(long n, int b = 256) { return int((n + b - 1) / b); }
+
+template <int NS, int NT> class Runner : public IRunner {
+ public:
+  int nprim() const override { return PF<NS>::N; }
+
+  hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable) override {
+    hipLaunchKernelGGL((k_prim<NS, NT>), dim3(nblocks(g.NP)), dim3(256), 0, st, g, w.mech, w.Q, w.qfs, w.prim,
+                       w.flags + FL_BAD, stoppable ? w.flags + FL_DONE : nullptr);
+    return hipGetLastError();
+  }
+
+  hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) override {
+    const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    hipLaunchKernelGGL((k_face_i<NS, NT>), dim3(nblocks(long(g.ni + 1) * g.nj)), dim3(256), 0, st, g, w.mech, w.prim,
+                       w.Fi, w.Ri, done);
+    hipLaunchKernelGGL((k_face_j<NS, NT>), dim3(nblocks(long(g.ni) * (g.nj + 1))), dim3(256), 0, st, g, w.mech,
+                       w.prim, w.Fj, w.Rj, w.qw, done);
+    return hipGetLastError();
+  }
+
+  hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
+                  bool stoppable) override {
+    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, w.src, w.flags + FL_SING};
+    const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    if (prec == 0)
+      hipLaunchKernelGGL((k_cell<NS, NT, double>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
+                         w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    else
+      hipLaunchKernelGGL((k_cell<NS, NT, float>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
+                         w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    return hipGetLastError();
+  }
+
+  hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable) override {
+    hipLaunchKernelGGL(k_norms<NS>, dim3(1), dim3(256), 0, st, w.part, w.nblk_cell, w.norms, stoppable ? w.hist : nullptr,
+                       it, w.hist_max, stoppable ? w.r0 : nullptr, tol, stoppable ? w.flags + FL_DONE : nullptr,
+                       w.flags + FL_ITDONE);
+    return hipGetLastError();
+  }
+
+  template <typename RT> hipError_t sweeps_t(const Geo &g, const WS &w, hipStream_t st, int mode, bool stoppable) {
+    SweepArgs a{w.prim, w.Ri, w.Rj, w.Dinv, w.b, w.dqs, w.dq, mode};
+    const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    const int K = g.ni + g.nj - 1;
+    for (int k = 0; k < K; ++k) {
+      int j0 = k - g.ni + 1 > 0 ? k - g.ni + 1 : 0, j1 = k < g.nj - 1 ? k : g.nj - 1;
+      int len = j1 - j0 + 1;
+      hipLaunchKernelGGL((k_sweep_fwd_hp<NS, NT, RT>), dim3(nblocks(len, 64)), dim3(64), 0, st, g, a, k, done);
+    }
+    for (int k = K - 1; k >= 0; --k) {
+      int j0 = k - g.ni + 1 > 0 ? k - g.ni + 1 : 0, j1 = k < g.nj - 1 ? k : g.nj - 1;
+      int len = j1 - j0 + 1;
+      hipLaunchKernelGGL((k_sweep_bwd_hp<NS, NT, RT>), dim3(nblocks(len, 64)), dim3(64), 0, st, g, a, k, done);
+    }
+    return hipGetLastError();
+  }
+
+  hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable) override {
+    return prec == 0 ? sweeps_t<double>(g, w, st, mode, stoppable) : sweeps_t<float>(g, w, st, mode, stoppable);
+  }
+
+  hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind, bool stoppable) override {
+    const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    if (prec == 0)
+      hipLaunchKernelGGL((k_update<NS, NT, double>), dim3(nblocks(g.N)), dim3(256), 0, st, g, w.mech, w.Q, w.dq, mode, kind,
+                         w.flags + FL_CLIP, w.flags + FL_BAD, done);
+    else
+      hipLaunchKernelGGL((k_update<NS, NT, float>), dim3(nblocks(g.N)), dim3(256), 0, st, g, w.mech, w.Q, w.dq, mode, kind,
+                         w.flags + FL_CLIP, w.flags + FL_BAD, done);
+    return hipGetLastError();
+  }
+
+  hipError_t q_from_prim_host(const Mech &m, const double *rs, double u, double v, double T, double Tv,
+                              double *q) override {
+    q_from_prim<NS, NT>(m, rs, u, v, T, Tv, q);
+    return hipSuccess;
+  }
+};
+
+}  // namespace csi

@@ -112,12 +112,14 @@ def _species_table(rows):
 
 # name, M, kind, theta_v, theta_r, sigma, g_el, h_form (0 K, J/mol), Sc  -- illustrative
 _AIR_NEUTRAL = [
-    ("N2", 28.0134e-3, MOLECULE, 3390.0, 2.88, 2.0, 1.0, 0.0, 0.70),
     ("O2", 31.9988e-3, MOLECULE, 2240.0, 2.08, 2.0, 3.0, 0.0, 0.72),
     ("NO", 30.0061e-3, MOLECULE, 2820.0, 2.45, 1.0, 4.0, 90.0e3, 0.71),
     ("N", 14.0067e-3, ATOM, 0.0, 0.0, 1.0, 4.0, 471.0e3, 0.60),
     ("O", 15.9994e-3, ATOM, 0.0, 0.0, 1.0, 9.0, 247.0e3, 0.62),
 ]
+# N2 closes the coupled system (the ns-th species follows from rho - sum of the
+# others), so it is kept last: it is the most abundant species everywhere.
+_N2 = [("N2", 28.0134e-3, MOLECULE, 3390.0, 2.88, 2.0, 1.0, 0.0, 0.70)]
 _AIR_IONS = [
     ("N2+", 28.0134e-3 - M_ELECTRON, MOLECULE, 3170.0, 2.78, 2.0, 2.0, 15.6 * EV_J_PER_MOL, 0.70),
     ("O2+", 31.9988e-3 - M_ELECTRON, MOLECULE, 2740.0, 2.42, 2.0, 4.0, 12.1 * EV_J_PER_MOL, 0.72),
@@ -165,9 +167,9 @@ def _reactions(names, hf, rxns):
 
 
 def air5(two_temp: int = 0) -> Mechanism:
-    """5-species air (N2, O2, NO, N, O), 17 reactions: three dissociations with
+    """5-species air (O2, NO, N, O, N2), 17 reactions: three dissociations with
     five explicit collision partners each and two exchange reactions."""
-    names, M, kind, tv, tr, sig, g, hf, sc, a, bb = _species_table(_AIR_NEUTRAL)
+    names, M, kind, tv, tr, sig, g, hf, sc, a, bb = _species_table(_AIR_NEUTRAL + _N2)
     diss = {"N2": ({"N": 2}, 5.0e21, -1.5), "O2": ({"O": 2}, 2.0e21, -1.5), "NO": ({"N": 1, "O": 1}, 5.0e15, 0.0)}
     rx = []
     for mol, (prod, A0, b0) in diss.items():
@@ -189,7 +191,7 @@ def air11(two_temp: int = 1) -> Mechanism:
     bodies, two exchanges, three associative ionisations, eleven charge
     exchanges and two electron-impact ionisations (the list is this
     workload's own; the paper only names the species)."""
-    names, M, kind, tv, tr, sig, g, hf, sc, a, bb = _species_table(_AIR_NEUTRAL + _AIR_IONS)
+    names, M, kind, tv, tr, sig, g, hf, sc, a, bb = _species_table(_AIR_NEUTRAL + _AIR_IONS + _N2)
     atoms3 = {"N": 3.0, "O": 3.0, "N+": 3.0, "O+": 3.0, "e-": 0.0}
     rx = [
         ({"N2": 1}, {"N": 2}, 5.0e21, -1.5, 1, True, atoms3),
@@ -261,6 +263,10 @@ def synthetic(ns: int = 20, nr: int = 60, seed: int = 3442) -> Mechanism:
         if len(comps) >= ns:
             break
         comps.append(tri[k])
+    extra = 0
+    while len(comps) < ns:  # isomers: a second species with an existing triatomic composition
+        comps.append(tri[order[extra % len(tri)]])
+        extra += 1
     comps = comps[:ns]
     hf_atom = rng.uniform(200e3, 500e3, 3)
     rows = []
@@ -275,6 +281,12 @@ def synthetic(ns: int = 20, nr: int = 60, seed: int = 3442) -> Mechanism:
             hf = float(np.dot(c, hf_atom)) - (nat - 1) * rng.uniform(300e3, 700e3)
             rows.append((f"X{k}", M, MOLECULE, float(rng.uniform(500.0, 4000.0)), float(rng.uniform(0.5, 3.0)),
                          2.0 if homo else 1.0, float(rng.integers(1, 4)), hf, float(rng.uniform(0.6, 0.8))))
+    # the first diatomic (the free stream's major species) closes the coupled
+    # system, so it is moved to the end
+    major = next(k for k, c in enumerate(comps) if sum(c) == 2)
+    order_ = [k for k in range(len(comps)) if k != major] + [major]
+    rows = [rows[k] for k in order_]
+    comps = [comps[k] for k in order_]
     names, M, kind, tv, tr, sig, g, hf, sc, a, bb = _species_table(rows)
     cidx = {c: k for k, c in enumerate(comps)}
     cand = []
@@ -304,6 +316,7 @@ def synthetic(ns: int = 20, nr: int = 60, seed: int = 3442) -> Mechanism:
         logA = rng.uniform(10.0, 22.0)
         bexp = rng.uniform(-2.0, 1.0)
         th = rng.uniform(0.0, 1.2e5)
+        th_min = None  # set below from the reaction enthalpy
         if cd[0] == "d":
             lhs = {names[cd[1]]: 1}
             rhs = {}
@@ -319,6 +332,10 @@ def synthetic(ns: int = 20, nr: int = 60, seed: int = 3442) -> Mechanism:
                 rhs[names[t]] = rhs.get(names[t], 0) + 1
             rx.append((lhs, rhs, 10.0 ** logA, bexp, 0, False, None, th))
     A, b, th, tctl, third, nu_f, nu_b, eff, labels = _reactions(names, hf, rx)
+    # the forward activation temperature is at least the reaction enthalpy / R_u,
+    # so that the backward direction has a non-negative activation energy
+    dH = ((nu_b - nu_f) @ hf) / R_U
+    th = np.maximum(th, dH)
     return Mechanism(names, M, kind, tv, tr, sig, g, hf, sc, a, bb, A, b, th, tctl, third, nu_f, nu_b, eff,
                      two_temp=0, reactions=labels)
 
@@ -394,8 +411,8 @@ class Config:
     def freestream_Y(self, mech: Mechanism) -> np.ndarray:
         Y = np.zeros(mech.ns)
         if self.mech == "syn20":
-            di = [k for k in range(mech.ns) if mech.kind[k] == MOLECULE][:2]
-            Y[di[0]], Y[di[1]] = 0.767, 0.233
+            di = [k for k in range(mech.ns - 1) if mech.kind[k] == MOLECULE and mech.names[k].count("X")][:1]
+            Y[mech.ns - 1], Y[di[0]] = 0.767, 0.233
         else:
             Y[mech.names.index("N2")] = 0.767
             Y[mech.names.index("O2")] = 0.233
