@@ -132,6 +132,11 @@ int csi_norm_history(csi_ctx *ctx, int n, double *hist);
  * arrays): rho_s [ns][n], u, v, T, Tv [n] -> q [nv][n] */
 int csi_prim_to_cons(csi_ctx *ctx, int n, const double *rho_s, const double *u, const double *v, const double *T,
                      const double *Tv, double *q);
+/* Sweep schedule: width 0 launches one kernel per i+j hyperplane; width 16 or 64
+ * runs each sweep as one persistent kernel with one wavefront per strip of that
+ * many columns (default 64 for ns <= 11, else 16), whose progress is published to the neighbouring
+ * strip every publish_every steps (1..64, default 4). */
+int csi_set_sweep(csi_ctx *ctx, int width, int publish_every);
 /* Phase timing of csi_step with HIP events on the context's stream (on = 1 to
  * enable).  csi_phase_times returns the accumulated milliseconds of the
  * phases [prim, faces, cell, norms, sweeps, update] and the number of timed

@@ -28,7 +28,8 @@ _ip = C.POINTER(C.c_int)
 EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_set_mechanism",
             "csi_set_freestream", "csi_workspace_bytes", "csi_bind_workspace", "csi_set_state", "csi_get_state",
             "csi_residual", "csi_implicit_op", "csi_consistency_correct", "csi_step", "csi_wall_heat_flux",
-            "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times"]
+            "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times",
+            "csi_set_sweep"]
 PHASES = ["prim", "faces", "cell", "norms", "sweeps", "update"]
 
 
@@ -227,6 +228,10 @@ class Solver:
         args = [_d(a) for a in (rho_s, u, v, T, Tv)]
         self._check(self.L.csi_prim_to_cons(self.ctx, n, *[p for _, p in args], q.ctypes.data_as(_dp)))
         return q
+
+    def set_sweep(self, width, publish_every=4):
+        """0: one launch per hyperplane; 16 or 64: persistent strip-wavefront kernels"""
+        self._check(self.L.csi_set_sweep(self.ctx, int(width), int(publish_every)))
 
     def set_timing(self, on=True):
         self._check(self.L.csi_set_timing(self.ctx, int(on)))

@@ -55,6 +55,8 @@ struct csi_ctx {
   WS w;
   Geo g;
   long it_global = 0;
+  int strip_w = 16;  // sweep schedule: 0 hyperplane launches, 16 / 64 persistent strips
+  int pub_every = 4;  // strip progress publication interval (steps)
   // phase timing (HIP events, created on first use)
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -93,6 +95,10 @@ Layout layout(const csi_ctx *c, int nprim) {
   const int nv = c->nv(), nsol = c->nsplit();
   const size_t ndinv = std::max<size_t>(size_t(c->nb()) * c->nb(), 6 + size_t(c->ns) * c->ns);
   const size_t nblk = (N + 255) / 256;
+  // per-cell sweep records: cell-major (N) or strip layout (up to the widest strip)
+  const StripMap sm = strip_map(c->ni, c->nj, 16), sm64 = strip_map(c->ni, c->nj, 64);
+  const size_t A = std::max<size_t>(N, std::max<size_t>(sm.LEN, sm64.LEN));
+  const size_t nstrip = std::max(sm.nstrip, sm64.nstrip);
   size_t sizes[] = {
       sizeof(Mech),                       // 0 mech
       N * 8, N * 8, N * 8, NN * 8, NN * 8, // 1-5 V xc yc xn yn
@@ -106,9 +112,13 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(nv) * N * 8, N * 8, size_t(nv) * N * 8,   // 19-21 R dtau src
       size_t(c->ni) * 8, 2 * nblk * 8, 2 * 8, 8,       // 22-25 qw part norms r0
       size_t(2) * HIST_MAX * 8,                       // 26 hist
-      size_t(nsol) * N * 8, size_t(nsol) * N * 8, size_t(nsol) * N * 8,  // 27-29 b dqs dq
-      ndinv * N * 8,                                  // 30 Dinv
+      size_t(nsol) * A * 8, size_t(nsol) * A * 8, size_t(nsol) * A * 8,  // 27-29 b dqs dq
+      ndinv * A * 8,                                  // 30 Dinv
       FL_N * 4,                                       // 31 flags
+      size_t(6 + 2 * c->ns) * A * 8,                  // 32 strip state records
+      size_t(16) * A * 8,                             // 33 strip face records
+      size_t(nstrip) * c->nj * nsol * 8,              // 34 strip-boundary pushes
+      size_t(2 * nstrip + 2) * 4,                     // 35 strip progress counters and tickets
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -219,6 +229,7 @@ int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
   c->run = r;
   c->ns = mm->ns;
   c->nt = mm->two_temp ? 2 : 1;
+  c->strip_w = mm->ns <= 11 ? 64 : 16;  // widest compiled strip (fewest strip boundaries)
   c->has_mech = true;
   c->has_fs = false;
   c->bound = false;
@@ -268,6 +279,13 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.hist = D(26);
   w.b = b + L.off[27]; w.dqs = b + L.off[28]; w.dq = b + L.off[29]; w.Dinv = b + L.off[30];
   w.flags = reinterpret_cast<int *>(b + L.off[31]);
+  w.state = b + L.off[32];
+  w.face = b + L.off[33];
+  w.bnd = b + L.off[34];
+  w.sync = reinterpret_cast<int *>(b + L.off[35]);
+  w.strip_w = c->strip_w;
+  w.pub_every = c->pub_every;
+  w.spin_limit = 4000000;
   w.nblk_cell = (c->N + 255) / 256;
   w.hist_max = HIST_MAX;
   Geo &g = c->g;
@@ -362,6 +380,7 @@ int csi_implicit_op(csi_ctx *c, int mode, int precision, int jac) {
   if (rc) return rc;
   int fl[FL_N];
   if ((rc = read_flags(c, fl))) return rc;
+  if (fl[FL_ABORT]) return c->fail(CSI_ERR_HIP, "implicit_op: a sweep wave timed out waiting for its neighbour");
   if (fl[FL_SING] != INT_MAX)
     return c->fail(CSI_ERR_SINGULAR, "singular diagonal block at cell " + std::to_string(fl[FL_SING]));
   c->last_mode = mode;
@@ -448,6 +467,10 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
           c->phase_ms[6] += 1.0;
         }
       }
+      if (fl[FL_ABORT]) {
+        if (s) *s = st;
+        return c->fail(CSI_ERR_HIP, "step: a sweep wave timed out waiting for its neighbour strip");
+      }
       if (fl[FL_BAD] != INT_MAX || fl[FL_SING] != INT_MAX) {
         st.bad_cell = fl[FL_BAD] != INT_MAX ? fl[FL_BAD] : fl[FL_SING];
         if (s) *s = st;
@@ -507,6 +530,20 @@ int csi_prim_to_cons(csi_ctx *c, int n, const double *rho_s, const double *u, co
   return CSI_OK;
 }
 
+int csi_set_sweep(csi_ctx *c, int width, int publish_every) {
+  if (!c) return CSI_ERR_ARG;
+  if (width != 0 && width != 16 && width != 64) return c->fail(CSI_ERR_ARG, "sweep width must be 0, 16 or 64");
+  if (width == 64 && c->ns > 11) return c->fail(CSI_ERR_UNSUPPORTED, "64-column strips are compiled for ns <= 11");
+  if (publish_every < 1 || publish_every > 64) return c->fail(CSI_ERR_ARG, "publish interval must be 1..64");
+  c->strip_w = width;
+  c->w.strip_w = width;
+  c->pub_every = publish_every;
+  c->w.pub_every = publish_every;
+  c->has_res = false;
+  c->has_dq = false;
+  return CSI_OK;
+}
+
 int csi_set_timing(csi_ctx *c, int on) {
   if (!c) return CSI_ERR_ARG;
   c->timing = on != 0;
@@ -560,14 +597,27 @@ int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
   }
   if (count < cnt) return c->fail(CSI_ERR_ARG, "buffer too small for " + n);
   if (src) return hip_check(c, hipMemcpy(out, src, cnt * 8, hipMemcpyDeviceToHost), "get");
-  if (c->last_prec == CSI_MIXED) {
-    std::vector<float> tmp(cnt);
-    int rc = hip_check(c, hipMemcpy(tmp.data(), rsrc, cnt * 4, hipMemcpyDeviceToHost), "get");
-    if (rc) return rc;
-    for (size_t k = 0; k < cnt; ++k) out[k] = tmp[k];
-    return CSI_OK;
+  // sweep records: cell-major or strip layout, FP64 or FP32
+  const size_t rows = cnt / N;
+  size_t stride = N;
+  StripMap sm{};
+  if (c->strip_w > 0) {
+    sm = strip_map(c->ni, c->nj, c->strip_w);
+    stride = sm.LEN;
   }
-  return hip_check(c, hipMemcpy(out, rsrc, cnt * 8, hipMemcpyDeviceToHost), "get");
+  const size_t esz = c->last_prec == CSI_MIXED ? 4 : 8;
+  std::vector<char> tmp(rows * stride * esz);
+  int rc = hip_check(c, hipMemcpy(tmp.data(), rsrc, tmp.size(), hipMemcpyDeviceToHost), "get");
+  if (rc) return rc;
+  for (size_t r_ = 0; r_ < rows; ++r_)
+    for (int j = 0; j < c->nj; ++j)
+      for (int i = 0; i < c->ni; ++i) {
+        size_t pos = c->strip_w > 0 ? size_t(strip_pos(sm, i, j)) : size_t(j) * c->ni + i;
+        size_t k = r_ * stride + pos;
+        out[r_ * N + size_t(j) * c->ni + i] =
+            esz == 4 ? double(reinterpret_cast<const float *>(tmp.data())[k]) : reinterpret_cast<const double *>(tmp.data())[k];
+      }
+  return CSI_OK;
 }
 
 }  // extern "C"

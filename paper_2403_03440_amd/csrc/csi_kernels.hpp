@@ -389,10 +389,12 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
 // mode 1: split (flow block in closed form, ns x ns species block)
 struct CellOut {
   double *R, *dtau, *part;     // part: per-block norm partials [2][nblocks]
-  void *Dinv;                  // coupled: [nb*nb][N]; split: DF [6][N] then DC [ns*ns][N]
-  void *b;                     // RHS [nsol][N]
+  void *Dinv;                  // coupled: [nb*nb][STR]; split: DF [6][STR] then DC [ns*ns][STR]
+  void *b;                     // RHS [nsol][STR]
+  void *state, *face;          // strip layout only: JVP state and face coefficients
   double *src;                 // optional source vector [nv][N] (debug)
   int *bad;
+  int strip_w;                 // 0: cell-major layout (stride N); W > 0: strip layout of width W
 };
 
 template <int NS, int NT, typename RT>
@@ -471,6 +473,12 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     prim_from_q<NS, NT>(m, q, P);
     double Vdt = Vp / dt;
     RT *bb = reinterpret_cast<RT *>(out.b);
+    long STR = g.N, pos = p;
+    if (out.strip_w > 0) {
+      int W = out.strip_w, sidx = i / W, l = i - sidx * W, NSTEP = g.nj + W - 1, nstrip = (g.ni + W - 1) / W;
+      STR = long(nstrip) * NSTEP * W;
+      pos = (long(sidx) * NSTEP + j + l) * W + l;
+    }
     if (mode == 0) {
       // coupled: dS_z/dz, z = (rho, m_x, m_y, rhoE, [rhoe_ve], rho_0..rho_{ns-2})
       // storage derivative of omega_s: dw/dq_j = dw_dr + dw_dT dT/dq_j + dw_dTv dTv/dq_j
@@ -491,22 +499,22 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
       for (int r = 0; r < NB; ++r)
 #pragma unroll
-        for (int c = 0; c < NB; ++c) Di[size_t(r * NB + c) * g.N + p] = RT(Ai[r][c]);
+        for (int c = 0; c < NB; ++c) Di[long(r * NB + c) * STR + pos] = RT(Ai[r][c]);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
-      bb[size_t(0) * g.N + p] = RT(-rsum);
-      bb[size_t(1) * g.N + p] = RT(-R[NS]);
-      bb[size_t(2) * g.N + p] = RT(-R[NS + 1]);
-      bb[size_t(3) * g.N + p] = RT(-R[NS + 2]);
-      if (NT == 2) bb[size_t(4) * g.N + p] = RT(-R[NS + 3]);
+      bb[0 * STR + pos] = RT(-rsum);
+      bb[1 * STR + pos] = RT(-R[NS]);
+      bb[2 * STR + pos] = RT(-R[NS + 1]);
+      bb[3 * STR + pos] = RT(-R[NS + 2]);
+      if (NT == 2) bb[4 * STR + pos] = RT(-R[NS + 3]);
 #pragma unroll
-      for (int s = 0; s < NS - 1; ++s) bb[size_t(NF + s) * g.N + p] = RT(-R[s]);
+      for (int s = 0; s < NS - 1; ++s) bb[long(NF + s) * STR + pos] = RT(-R[s]);
     } else {
       double dF = Vdt + 0.5 * slam + svF;
       double dC = Vdt + 0.5 * sU + svC;
       RT *DF = reinterpret_cast<RT *>(out.Dinv);
-      RT *DC = DF + size_t(6) * g.N;
+      RT *DC = DF + 6 * STR;
       // flow block: scalar rows, plus the rho e_ve row -V d omega_ve/dQ_F (frozen Y)
       double df6[6];
       df6[0] = 1.0 / dF;
@@ -521,7 +529,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         df6[5] = 1.0 / piv;
       }
 #pragma unroll
-      for (int k = 0; k < 6; ++k) DF[size_t(k) * g.N + p] = RT(df6[k]);
+      for (int k = 0; k < 6; ++k) DF[long(k) * STR + pos] = RT(df6[k]);
       double A[NS][NS], Ai[NS][NS];
 #pragma unroll
       for (int r = 0; r < NS; ++r)
@@ -532,17 +540,60 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
       for (int r = 0; r < NS; ++r)
 #pragma unroll
-        for (int c = 0; c < NS; ++c) DC[size_t(r * NS + c) * g.N + p] = RT(Ai[r][c]);
+        for (int c = 0; c < NS; ++c) DC[long(r * NS + c) * STR + pos] = RT(Ai[r][c]);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
-      bb[size_t(0) * g.N + p] = RT(-rsum);
-      bb[size_t(1) * g.N + p] = RT(-R[NS]);
-      bb[size_t(2) * g.N + p] = RT(-R[NS + 1]);
-      bb[size_t(3) * g.N + p] = RT(-R[NS + 2]);
-      if (NT == 2) bb[size_t(4) * g.N + p] = RT(-R[NS + 3]);
+      bb[0 * STR + pos] = RT(-rsum);
+      bb[1 * STR + pos] = RT(-R[NS]);
+      bb[2 * STR + pos] = RT(-R[NS + 1]);
+      bb[3 * STR + pos] = RT(-R[NS + 2]);
+      if (NT == 2) bb[4 * STR + pos] = RT(-R[NS + 3]);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) bb[size_t(NF + s) * g.N + p] = RT(-R[s]);
+      for (int s = 0; s < NS; ++s) bb[long(NF + s) * STR + pos] = RT(-R[s]);
+    }
+    if (out.strip_w > 0) {
+      // JVP state of this cell and the coefficients of its four pushes
+      RT *st = reinterpret_cast<RT *>(out.state);
+      RT *fc = reinterpret_cast<RT *>(out.face);
+      st[0 * STR + pos] = RT(P.u);
+      st[1 * STR + pos] = RT(P.v);
+      st[2 * STR + pos] = RT(P.H);
+      st[3 * STR + pos] = RT(P.eve);
+      st[4 * STR + pos] = RT(P.pE);
+      st[5 * STR + pos] = RT(P.pv);
+      if (mode == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          st[long(6 + s) * STR + pos] = RT(P.Y[s]);
+          st[long(6 + NS + s) * STR + pos] = RT(P.pr[s]);
+        }
+      } else {
+        double prY = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) prY += P.pr[s] * P.Y[s];
+        st[6 * STR + pos] = RT(prY);
+      }
+      const int rv = mode == 0 ? R_LVK : R_LVF;
+      // E face = i-face (i+1, j), N face = j-face (i, j+1): outward normals of the
+      // receiving neighbours are -n; W face = i-face (i, j), S face = j-face (i, j): +n
+      const double SEh = 0.5 * SE, SNh = 0.5 * SN, SWh = 0.5 * SW, SSh = 0.5 * SS;
+      fc[0 * STR + pos] = RT(-SEh * g.fi_nx[fE]);
+      fc[1 * STR + pos] = RT(-SEh * g.fi_ny[fE]);
+      fc[2 * STR + pos] = RT(-SNh * g.fj_nx[fN]);
+      fc[3 * STR + pos] = RT(-SNh * g.fj_ny[fN]);
+      fc[4 * STR + pos] = RT(SWh * g.fi_nx[fW]);
+      fc[5 * STR + pos] = RT(SWh * g.fi_ny[fW]);
+      fc[6 * STR + pos] = RT(SSh * g.fj_nx[fS]);
+      fc[7 * STR + pos] = RT(SSh * g.fj_ny[fS]);
+      fc[8 * STR + pos] = RT(SEh * Ri[size_t(R_LAM) * nfi + fE] + SE * Ri[size_t(rv) * nfi + fE]);
+      fc[9 * STR + pos] = RT(SNh * Rj[size_t(R_LAM) * nfj + fN] + SN * Rj[size_t(rv) * nfj + fN]);
+      fc[10 * STR + pos] = RT(SWh * Ri[size_t(R_LAM) * nfi + fW] + SW * Ri[size_t(rv) * nfi + fW]);
+      fc[11 * STR + pos] = RT(SSh * Rj[size_t(R_LAM) * nfj + fS] + SS * Rj[size_t(rv) * nfj + fS]);
+      fc[12 * STR + pos] = RT(SEh * Ri[size_t(R_UABS) * nfi + fE] + SE * Ri[size_t(R_LVC) * nfi + fE]);
+      fc[13 * STR + pos] = RT(SNh * Rj[size_t(R_UABS) * nfj + fN] + SN * Rj[size_t(R_LVC) * nfj + fN]);
+      fc[14 * STR + pos] = RT(SWh * Ri[size_t(R_UABS) * nfi + fW] + SW * Ri[size_t(R_LVC) * nfi + fW]);
+      fc[15 * STR + pos] = RT(SSh * Rj[size_t(R_UABS) * nfj + fS] + SS * Rj[size_t(R_LVC) * nfj + fS]);
     }
     }
   }

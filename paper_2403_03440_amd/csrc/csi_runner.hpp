@@ -2,7 +2,7 @@
 // count and the temperature model; instantiated per species count in
 // csi_inst.hip and dispatched through the IRunner interface.
 #pragma once
-#include "csi_sweep.hpp"
+#include "csi_strip.hpp"
 
 namespace csi {
 
@@ -12,10 +12,15 @@ struct WS {
   double *V, *xc, *yc, *xn, *yn, *fi_nx, *fi_ny, *fi_S, *fj_nx, *fj_ny, *fj_S;
   double *qfs, *Q, *prim, *Fi, *Fj, *Ri, *Rj, *R, *dtau, *src, *qw, *part, *norms, *r0, *hist;
   void *b, *dqs, *dq, *Dinv;
+  void *state, *face, *bnd;  // strip-layout sweep records and strip-boundary pushes
+  int *sync;                 // [nstrip] fwd progress, [nstrip] bwd progress, [2] tickets
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
+  int strip_w;               // 0: one launch per hyperplane; 16 or 64: persistent strip kernels
+  int pub_every;             // strip progress published every this many steps
+  long spin_limit;
 };
-enum { FL_BAD = 0, FL_DONE = 1, FL_ITDONE = 2, FL_CLIP = 3, FL_SING = 4, FL_N = 8 };
+enum { FL_BAD = 0, FL_DONE = 1, FL_ITDONE = 2, FL_CLIP = 3, FL_SING = 4, FL_ABORT = 5, FL_N = 8 };
 
 class IRunner {
  public:
@@ -58,7 +63,7 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                   bool stoppable) override {
-    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, w.src, w.flags + FL_SING};
+    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, w.state, w.face, w.src, w.flags + FL_SING, w.strip_w};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
       hipLaunchKernelGGL((k_cell<NS, NT, double>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
@@ -77,8 +82,36 @@ template <int NS, int NT> class Runner : public IRunner {
   }
 
   template <typename RT> hipError_t sweeps_t(const Geo &g, const WS &w, hipStream_t st, int mode, bool stoppable) {
-    SweepArgs a{w.prim, w.Ri, w.Rj, w.Dinv, w.b, w.dqs, w.dq, mode};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    if (w.strip_w > 0) {
+      StripMap sm = strip_map(g.ni, g.nj, w.strip_w);
+      int *prog = w.sync, *progb = w.sync + sm.nstrip, *ticket = w.sync + 2 * sm.nstrip;
+      StripArgs a{w.b, w.Dinv, w.state, w.face, w.dqs, w.dq, w.bnd, prog, progb, ticket, w.flags + FL_ABORT, mode,
+                  w.pub_every, w.spin_limit};
+      hipLaunchKernelGGL(k_zero_ints<NS>, dim3(1), dim3(64), 0, st, w.sync, 2 * sm.nstrip + 2, done);
+      const dim3 gr(sm.nstrip), bl(64);
+      if (w.strip_w == 16 || NS > 11) {  // 64-column strips are compiled for ns <= 11 only
+        if (mode == 0) {
+          hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
+          hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
+        } else {
+          hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
+          hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
+        }
+      } else {
+        if constexpr (NS <= 11) {
+          if (mode == 0) {
+            hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
+            hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
+          } else {
+            hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
+            hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
+          }
+        }
+      }
+      return hipGetLastError();
+    }
+    SweepArgs a{w.prim, w.Ri, w.Rj, w.Dinv, w.b, w.dqs, w.dq, mode};
     const int K = g.ni + g.nj - 1;
     for (int k = 0; k < K; ++k) {
       int j0 = k - g.ni + 1 > 0 ? k - g.ni + 1 : 0, j1 = k < g.nj - 1 ? k : g.nj - 1;
@@ -101,10 +134,10 @@ template <int NS, int NT> class Runner : public IRunner {
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
       hipLaunchKernelGGL((k_update<NS, NT, double>), dim3(nblocks(g.N)), dim3(256), 0, st, g, w.mech, w.Q, w.dq, mode, kind,
-                         w.flags + FL_CLIP, w.flags + FL_BAD, done);
+                         w.flags + FL_CLIP, w.flags + FL_BAD, done, w.strip_w);
     else
       hipLaunchKernelGGL((k_update<NS, NT, float>), dim3(nblocks(g.N)), dim3(256), 0, st, g, w.mech, w.Q, w.dq, mode, kind,
-                         w.flags + FL_CLIP, w.flags + FL_BAD, done);
+                         w.flags + FL_CLIP, w.flags + FL_BAD, done, w.strip_w);
     return hipGetLastError();
   }
 

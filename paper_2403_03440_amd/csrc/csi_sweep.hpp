@@ -225,17 +225,23 @@ template <int NS, int NT, typename RT>
 __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ mech, double *__restrict__ Q,
                                                 const void *__restrict__ dqv, int mode,
                                                 int kind, int *__restrict__ nclip, int *__restrict__ bad,
-                                                const int *__restrict__ done) {
+                                                const int *__restrict__ done, int strip_w) {
   using D = Dims<NS, NT>;
   constexpr int NF = D::nf;
   if (done && *done) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.N) return;
   const RT *dq = reinterpret_cast<const RT *>(dqv);
+  long STR = g.N, pos = p;
+  if (strip_w > 0) {
+    int W = strip_w, i = p % g.ni, j = p / g.ni, sidx = i / W, l = i - sidx * W, NSTEP = g.nj + W - 1;
+    STR = long((g.ni + W - 1) / W) * NSTEP * W;
+    pos = (long(sidx) * NSTEP + j + l) * W + l;
+  }
   double rs[NS], rho = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) { rs[s] = Q[size_t(s) * g.N + p]; rho += rs[s]; }
-  double drho = double(dq[p]);
+  double drho = double(dq[pos]);
   double target = rho + drho;
   double nr[NS];
   bool clip = false;
@@ -243,7 +249,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
     double sum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s) {
-      double d = double(dq[size_t(NF + s) * g.N + p]);
+      double d = double(dq[long(NF + s) * STR + pos]);
       nr[s] = rs[s] + d;
       sum += d;
     }
@@ -251,14 +257,14 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   } else if (kind == 1) {
     double sum = 0.0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sum += double(dq[size_t(NF + s) * g.N + p]);
+    for (int s = 0; s < NS; ++s) sum += double(dq[long(NF + s) * STR + pos]);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) nr[s] = rs[s] + double(dq[size_t(NF + s) * g.N + p]) + (rs[s] / rho) * (drho - sum);
+    for (int s = 0; s < NS; ++s) nr[s] = rs[s] + double(dq[long(NF + s) * STR + pos]) + (rs[s] / rho) * (drho - sum);
   } else {
     double t[NS], sum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      double v = rs[s] + double(dq[size_t(NF + s) * g.N + p]);
+      double v = rs[s] + double(dq[long(NF + s) * STR + pos]);
       if (v < 0.0) clip = true;
       t[s] = v > 0.0 ? v : 0.0;
       sum += t[s];
@@ -282,12 +288,12 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   if (!(target > 0.0) && bad) atomicMin(bad, p);
 #pragma unroll
   for (int s = 0; s < NS; ++s) Q[size_t(s) * g.N + p] = nr[s];
-  Q[size_t(NS) * g.N + p] += double(dq[size_t(1) * g.N + p]);
-  Q[size_t(NS + 1) * g.N + p] += double(dq[size_t(2) * g.N + p]);
-  Q[size_t(NS + 2) * g.N + p] += double(dq[size_t(3) * g.N + p]);
+  Q[size_t(NS) * g.N + p] += double(dq[1 * STR + pos]);
+  Q[size_t(NS + 1) * g.N + p] += double(dq[2 * STR + pos]);
+  Q[size_t(NS + 2) * g.N + p] += double(dq[3 * STR + pos]);
   if (NT == 2) {
     // positivity of the vibrational-electronic energy: floor at Tv = TV_FLOOR
-    double eve = Q[size_t(NS + 3) * g.N + p] + double(dq[size_t(4) * g.N + p]), fl = 0.0;
+    double eve = Q[size_t(NS + 3) * g.N + p] + double(dq[4 * STR + pos]), fl = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) fl += nr[s] * eve_s(*mech, s, TV_FLOOR);
     if (eve < fl) {

@@ -247,3 +247,41 @@ def test_bitwise_determinism():
         s.step(1, 2, 5.0, 20, cfl_ramp=10)
         outs.append(s.get_state())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("name,ni,nj", [("air5_2T", 32, 24), ("air11_2T", 32, 24)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sweep_schedules(name, ni, nj, mode):
+    """The persistent strip kernels (16- and 64-column strips) and the
+    one-launch-per-hyperplane schedule all match the oracle; the two strip
+    widths give bitwise identical increments (same per-cell arithmetic)."""
+    csi = _csi()
+    m, (o, s, q0) = make_pair(name, ni, nj, "evolved")
+    g = groups_inc(m, mode)
+    noise = oracle_noise(o, q0, mode, 10.0, g)
+    tol = np.maximum(TOL64, 10.0 * noise)
+    out = {}
+    for w in (0, 16, 64):
+        s.set_sweep(w)
+        s.set_state(q0)
+        s.residual(10.0)
+        s.implicit_op(mode, csi.FP64)
+        out[w] = s.get("dq", mode)
+        assert np.all(normwise(out[w], o.get("dq", mode), g) <= tol), w
+    assert np.array_equal(out[16], out[64])
+
+
+@pytest.mark.parametrize("ni,nj,w", [(37, 11, 16), (37, 11, 64), (70, 5, 64), (16, 9, 16)])
+def test_strip_ragged(ni, nj, w):
+    """strip counts that do not divide the grid width"""
+    csi = _csi()
+    m = mech_by_name("air5_1T")
+    o, s, q0 = pair(m, ni, nj, seed=13, T_range=(300.0, 2500.0), speed=800.0)
+    s.set_sweep(w)
+    for mode in (0, 1):
+        g = groups_inc(m, mode)
+        noise = oracle_noise(o, q0, mode, 5.0, g)
+        s.set_state(q0)
+        s.residual(5.0)
+        s.implicit_op(mode, csi.FP64)
+        assert np.all(normwise(s.get("dq", mode), o.get("dq", mode), g) <= np.maximum(TOL64, 10.0 * noise))
