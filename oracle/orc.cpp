@@ -37,8 +37,8 @@ struct Face {
   double lvF = 0, lvC = 0, lvK = 0;   // viscous radii nu_f S_f / V_f (flow, species, coupled)
 };
 
-constexpr double CSTEP = 1e-25;
-constexpr double TV_FLOOR = 50.0;  // lower bound of Tv after an update  // complex-step size (relative to max(|x|, 1))
+constexpr double CSTEP = 1e-25;     // complex-step size (relative to max(|x|, 1))
+constexpr double TV_FLOOR = 50.0;  // lower bound of Tv after an update
 
 }  // namespace
 
