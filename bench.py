@@ -1,70 +1,210 @@
 """Benchmark of the implicit-solver hot path on one MI355X.
 
-A step is one pseudo-time iteration of the whole path (primitives, residual
-with chemistry, diagonal blocks, LU-SGS forward/backward sweeps, consistency
-correction and update, norms) over the 512 x 256 polar blunt-body grid with
-two-temperature 5-species air at CFL 100 (synthetic free-stream start).
+A step is one pseudo-time iteration of the whole path: primitives, residual
+with chemistry, local time step, diagonal blocks with the source Jacobian, the
+LU-SGS forward and backward sweeps, the consistency correction and update, and
+the residual norms.  The default workload is the 512 x 256 polar blunt-body
+grid with two-temperature 5-species air at CFL 100 from a uniform free stream
+(synthetic input; there is no dataset).
+
+Reported per variant (coupled / split, FP64 / mixed, exact / surrogate
+species Jacobian block):
+  * cell-iterations per second over K timed steps after W warm-up steps;
+  * time and iterations to a 1e-8 drop of the density residual, from the free
+    stream, with the same CFL ramp for every variant.
+The surrogate network is trained first on samples of the exact solver's own
+iterations (collection and training times reported separately).  The headline
+`value` is the split mixed-precision solver with the surrogate block.
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic bytes per cell-iteration (state read twice and written once,
-# geometry read twice, sweep intermediate written and read once)
-GEOM_WORDS = 5
+GEOM_WORDS = 5  # cell volume + four face lengths/normals summarised as one word each
+HBM_PEAK_GBS = 8000.0
+VARIANTS = {  # name: (mode, correction kind, precision, species Jacobian 0 exact / 1 surrogate)
+    "split64": (1, 2, 0, 0), "coupled64": (0, 0, 0, 0), "splitmixed": (1, 2, 1, 0), "coupledmixed": (0, 0, 1, 0),
+    "splitmixed_mlp": (1, 2, 1, 1)}
+HEADLINE = "splitmixed_mlp"
+SWEEP_SOURCES = ["csi_strip.hpp", "csi_sweep.hpp", "csi_phys.hpp"]
 
 
-def b_alg(m, mode, precision):
-    nsol = m.nb if mode == 0 else m.nf + m.ns
-    w_sweep = 8 if precision == 0 else 4
-    return (3 * m.nv + 2 * GEOM_WORDS) * 8 + 2 * nsol * w_sweep
+def nsol(m, mode):
+    return m.nb if mode == 0 else m.nf + m.ns
 
 
-def run_variant(csi, cfg, m, x, y, fs, q0, mode, kind, precision, steps, warmup):
-    import torch
+def b_alg_iter(m, mode, precision):
+    """Algorithmic bytes per cell-iteration of the whole path: state read twice
+    and written once, geometry read twice, the sweep intermediate written and
+    read once."""
+    w = 8 if precision == 0 else 4
+    return (3 * m.nv + 2 * GEOM_WORDS) * 8 + 2 * nsol(m, mode) * w
+
+
+def b_alg_sweep(m, mode, precision):
+    """Algorithmic bytes per cell of one sweep launch: the cell's state and
+    geometry (from which its diagonal block and face operators follow), the
+    incoming right-hand side (b or dQ*) and the outgoing increment."""
+    w = 8 if precision == 0 else 4
+    return (m.nv + GEOM_WORDS) * 8 + 2 * nsol(m, mode) * w
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_03440_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    that summary was taken on the current sweep sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    hm = re.search(r"source hash:\s*`?([0-9a-f]{16})", txt)
+    tm = re.search(r"HBM bytes per launch:\s*([0-9.eE+]+)", txt)
+    if not hm or not tm or hm.group(1) != sweep_source_hash():
+        return None
+    return float(tm.group(1))
+
+
+def new_solver(csi, I, cfg, m, x, y, fs, sur=None):
     s = csi.Solver((x, y), m, fs)
-    s.set_state(q0)
+    s.set_state(s.initial_state(*I.initial_prims(cfg, m)))
+    if sur is not None:
+        s.set_surrogate(sur["params"], sur["scales"])
+    return s
+
+
+def train_surrogate(csi, I, cfg, m, x, y, fs, epochs, snapshots):
+    """Samples from the exact split mixed solver's first iterations (every 5th
+    iteration, all cells), then training on the GPU; both timed."""
+    import torch
+    from paper_2403_03440_amd import surrogate as S
+    s = new_solver(csi, I, cfg, m, x, y, fs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xr, jc, its = S.collect(s, (1, 2, 1), cfg.cfl, snapshots * s.N, every=5)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params, scales, hist = S.train(xr, jc, epochs=epochs, batch=4096, lr=1e-3, seed=cfg.seed + 1,
+                                   log=lambda msg: print("# " + msg, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"samples": int(xr.shape[0]), "collect_iterations": its, "collect_s": t1 - t0, "train_s": t2 - t1,
+            "epochs": epochs, "train_loss": hist[-1][1], "val_loss": hist[-1][2], "first_val_loss": hist[0][2],
+            "network": f"{m.ns + 3}-64-64-{m.ns * m.ns}, BF16 operands, FP32 accumulation"}
+    del s, xr, jc
+    return {"params": params, "scales": scales}, info
+
+
+def throughput(csi, I, cfg, m, x, y, fs, variant, steps, warmup, sur=None):
+    import torch
+    mode, kind, prec, jac = VARIANTS[variant]
+    s = new_solver(csi, I, cfg, m, x, y, fs, sur if jac else None)
     s.set_timing(True)
     if warmup:
-        s.step(mode, kind, cfg.cfl, warmup, precision=precision, cfl_ramp=100, check_every=max(warmup, 1))
+        s.step(mode, kind, cfg.cfl, warmup, precision=prec, jac=jac, cfl_ramp=100, check_every=warmup)
     s.phase_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = s.step(mode, kind, cfg.cfl, steps, precision=precision, cfl_ramp=100, check_every=steps)
+    st = s.step(mode, kind, cfg.cfl, steps, precision=prec, jac=jac, cfl_ramp=100, check_every=steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ph = s.phase_times()
-    return {"seconds": dt, "iters": st["iters"], "cell_iters_per_s": cfg.ni * cfg.nj * st["iters"] / dt,
-            "ms_per_step": 1e3 * dt / max(st["iters"], 1), "phases_ms": ph, "stats": st}
+    n = max(st["iters"], 1)
+    out = {"seconds": dt, "iters": st["iters"], "cell_iters_per_s": cfg.ni * cfg.nj * st["iters"] / dt,
+           "ms_per_step": 1e3 * dt / n, "phases_ms_per_iter": {k: v["ms_per_iter"] for k, v in ph.items()
+                                                                 if isinstance(v, dict)},
+           "b_alg_per_cell_iter": b_alg_iter(m, mode, prec)}
+    if jac:
+        out["surrogate_accept_frac"] = 1.0 - st["n_dd_fallback"] / float(cfg.ni * cfg.nj * n)
+    return out
 
 
-def cpu_baseline(cfg, m, x, y, fs, q0, budget_s=20.0):
-    """The oracle on the host cores over a bounded sample: whole c2-size
-    iterations (split, CC2) until about budget_s seconds have passed."""
+def converge(csi, I, cfg, m, x, y, fs, variant, tol, max_iter, sur=None):
+    import torch
+    mode, kind, prec, jac = VARIANTS[variant]
+    s = new_solver(csi, I, cfg, m, x, y, fs, sur if jac else None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    st = None
+    fallback, off_at = 0, None
+    while done < max_iter:
+        st = s.step(mode, kind, cfg.cfl, min(1000, max_iter - done), precision=prec, jac=jac, cfl_ramp=100,
+                    tol=tol, check_every=50)
+        fallback += st["n_dd_fallback"]
+        if st["surrogate_off_at"] >= 0 and off_at is None:
+            off_at = st["surrogate_off_at"]
+        done += st["iters"]
+        print(f"# {variant}: {done} iterations, drop {st['r_last'] / st['r0']:.3e}, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        if st["converged"]:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, qs = s.wall_heat_flux()
+    out = {"tol": tol, "converged": bool(st["converged"]), "iters": done, "seconds": dt,
+           "drop": st["r_last"] / st["r0"], "q_stag_W_m2": qs}
+    if jac:
+        out["surrogate_accept_frac"] = 1.0 - fallback / float(cfg.ni * cfg.nj * max(done, 1))
+        out["surrogate_off_at"] = off_at
+    return out
+
+
+def oracle_threads():
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(n, 1)
+
+
+def cpu_baseline(I, cfg, m, x, y, fs, budget_s=20.0):
+    """The oracle on the host cores over a bounded sample: whole iterations of
+    the same workload (split, CC2, FP64) from the free stream until about
+    budget_s seconds have passed."""
     from oracle import orc
-    threads = os.cpu_count() or 1
+    threads = oracle_threads()
     o = orc.setup((x, y), m, fs, threads=threads)
-    o.set_state(q0)
+    o.set_state(o.prim_to_cons(*I.initial_prims(cfg, m)))
     t0 = time.perf_counter()
     n = 0
     while True:
         o.step(1, 2, cfg.cfl, 1, ramp=100, it0=n)
         n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 50:
+        if time.perf_counter() - t0 > budget_s or n >= 200:
             break
     dt = time.perf_counter() - t0
     return {"value": cfg.ni * cfg.nj * n / dt, "unit": "cell-iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} split-CC2 FP64 iterations of the {cfg.ni}x{cfg.nj} workload from the free stream"}
+            "sample": f"first {n} split-CC2 FP64 iterations of the {cfg.ni}x{cfg.nj} workload from the free "
+                      f"stream ({dt:.1f} s, {threads} OpenMP threads)"}
+
+
+def copy_probe(gib=1.0, reps=3):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"# copy probe: {reps} copies of {4 * n} bytes", file=sys.stderr, flush=True)
 
 
 def main():
@@ -73,11 +213,17 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--variants", default="splitmixed_mlp,splitmixed,split64,coupled64,coupledmixed")
+    ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
+    ap.add_argument("--snapshots", type=int, default=16, help="surrogate training snapshots (all cells each)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=12000)
+    ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="split64,coupled64,splitmixed")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print("bench.py: this implementation runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -88,30 +234,38 @@ def main():
     m = cfg.mechanism()
     x, y = cfg.grid()
     fs = I.freestream_prims(cfg, m)
-    # conservative initial state from the library's own conversion on the device
-    s0 = csi.Solver((x, y), m, fs)
-    q0 = s0.initial_state(*I.initial_prims(cfg, m))
-    del s0
-    variants = {"split64": (1, 2, 0), "coupled64": (0, 0, 0), "splitmixed": (1, 2, 1), "coupledmixed": (0, 0, 1)}
-    res = {}
-    for v in args.variants.split(","):
-        mode, kind, prec = variants[v]
-        print(f"# running {v}", file=sys.stderr, flush=True)
-        res[v] = run_variant(csi, cfg, m, x, y, fs, q0, mode, kind, prec, args.steps, args.warmup)
-        res[v]["b_alg"] = b_alg(m, mode, prec)
-    head = res.get("split64") or next(iter(res.values()))
     N = cfg.ni * cfg.nj
-    # roofline of the dominant phase of the headline variant (event-timed inside the library)
-    ph = head["phases_ms"]
-    dom = max(ph, key=lambda k: ph[k]["ms"])
-    per_iter_ms = ph[dom]["ms"] / max(head["iters"], 1)
-    alg_bytes = {"sweeps": 2 * 2 * (m.nf + m.ns) * 8 * N, "cell": (m.nv + m.nv + 1 + (m.nf + m.ns)) * 8 * N}
-    traffic_bytes = alg_bytes.get(dom)
-    roof = None
-    if traffic_bytes is not None:
-        ach = traffic_bytes / (per_iter_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
-                "traffic": None, "kernel": dom, "ms_per_launch_group": per_iter_ms}
+    names = [v for v in args.variants.split(",") if v]
+    if HEADLINE not in names:
+        names.insert(0, HEADLINE)
+    sur, sur_info = None, None
+    if any(VARIANTS[v][3] for v in names):
+        print("# surrogate: sampling and training", file=sys.stderr, flush=True)
+        sur, sur_info = train_surrogate(csi, I, cfg, m, x, y, fs, args.epochs, args.snapshots)
+    res = {}
+    for v in names:
+        print(f"# throughput {v}", file=sys.stderr, flush=True)
+        res[v] = throughput(csi, I, cfg, m, x, y, fs, v, args.steps, args.warmup, sur)
+    if not args.no_converge:
+        for v in names:
+            res[v]["to_tol"] = converge(csi, I, cfg, m, x, y, fs, v, args.tol, args.max_iter, sur)
+    if args.copy_probe:
+        copy_probe()
+    head = res[HEADLINE]
+    mode, _, prec, _ = VARIANTS[HEADLINE]
+    ph = head["phases_ms_per_iter"]
+    kernel = "sweep_fwd" if ph["sweep_fwd"] >= ph["sweep_bwd"] else "sweep_bwd"
+    ms_launch = ph[kernel]
+    bytes_launch = b_alg_sweep(m, mode, prec) * N
+    ach = bytes_launch / (ms_launch * 1e-3) / 1e9
+    traffic = measured_traffic(kernel, cfg.name)
+    chain = cfg.ni + cfg.nj - 1
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": kernel, "ms_per_launch": ms_launch, "alg_bytes_per_launch": bytes_launch,
+            "hyperplane_steps_per_launch": chain, "us_per_hyperplane_step": 1e3 * ms_launch / chain}
+    whole = {"alg_GBs": b_alg_iter(m, mode, prec) * head["cell_iters_per_s"] / 1e9}
+    whole["frac"] = whole["alg_GBs"] / HBM_PEAK_GBS
+    dtype = "f32+f64" if prec == 1 else "f64"
     out = {
         "metric": "cell-iters/s & time-to-1e-8 residual: split vs coupled, FP64 vs mixed+MLP",
         "value": head["cell_iters_per_s"],
@@ -119,16 +273,20 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.ni}x{cfg.nj} polar blunt body, {m.ns}-species air "
-                               f"{'2T' if m.two_temp else '1T'}, CFL {cfg.cfl:g}, split FP64 + CC2",
+                               f"{'2T' if m.two_temp else '1T'}, CFL {cfg.cfl:g} (ramp over 100 iterations), "
+                               f"split solver, FP32 sweeps + FP64 residual/chemistry/CC2, species Jacobian block "
+                               f"from the BF16 surrogate network with exact fallback, uniform free-stream start",
                    "cells": N},
-        "variants": {k: {kk: vv for kk, vv in r.items() if kk != "stats"} for k, r in res.items()},
         "roofline": roof,
+        "whole_iteration_hbm": whole,
+        "variants": res,
+        "surrogate_training": sur_info,
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, m, x, y, fs, q0)
+        out["cpu_baseline"] = cpu_baseline(I, cfg, m, x, y, fs)
     print(json.dumps(out))
 
 

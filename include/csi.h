@@ -85,6 +85,8 @@ typedef struct {
   int n_clipped;   /* cells with a clipped partial density */
   int bad_cell;    /* first non-physical cell, or -1 */
   double r0, r_last;
+  long long n_dd_fallback; /* cell-iterations whose surrogate block failed the dominance check (exact used) */
+  int surrogate_off_at;    /* iteration at which the stall policy switched the surrogate off, or -1 */
 } csi_step_stats;
 
 int csi_create(csi_ctx **ctx, int device, void *hip_stream);
@@ -139,15 +141,83 @@ int csi_prim_to_cons(csi_ctx *ctx, int n, const double *rho_s, const double *u, 
 int csi_set_sweep(csi_ctx *ctx, int width, int publish_every);
 /* Phase timing of csi_step with HIP events on the context's stream (on = 1 to
  * enable).  csi_phase_times returns the accumulated milliseconds of the
- * phases [prim, faces, cell, norms, sweeps, update] and the number of timed
- * iterations in ms[6]; reset = 1 clears the accumulators. */
+ * phases [prim, faces, cell, norms, sweep_fwd, sweep_bwd, update] (ms[0..6])
+ * and the number of timed iterations in ms[7]; reset = 1 clears the
+ * accumulators.  ms must hold 8 doubles. */
 int csi_set_timing(csi_ctx *ctx, int on);
 int csi_phase_times(csi_ctx *ctx, double *ms, int reset);
 
 /* Debug / parity access to named workspace arrays, copied to host as FP64:
  * "R" [nv][N], "dtau" [N], "src" [nv][N], "b" "dqs" "dq" [nsol][N], "T" "Tv" "p" "c" [N],
- * "qw" [ni], "Dinv" (coupled [nb*nb][N]; split [6 + ns*ns][N]). */
+ * "qw" [ni], "Dinv" (coupled [nb*nb][N]; split [6 + ns*ns][N]), "Jsur" [ns*ns][N]
+ * (surrogate species block of the last surrogate iteration). */
 int csi_get_array(csi_ctx *ctx, const char *name, double *out, size_t count);
+
+/* ------------------------------------------------------------------------
+ * Surrogate of the split species block J_C = d omega_s / d rho_r at fixed T,
+ * Tv (the chemical source Jacobian that the species diagonal block of Section
+ * 2.3 carries).  Network: x -> tanh(W1 x + b1) -> tanh(W2 h1 + b2) -> W3 h2 + b3,
+ * hidden width 64, n_in <= 64 inputs, n_out <= 1024 outputs; BF16 operands,
+ * FP32 accumulation on the matrix cores, FP32 master parameters
+ * [W1 (64 x n_in) | b1 | W2 (64 x 64) | b2 | W3 (n_out x 64) | b3] (row-major).
+ * Features x_raw = (ln T, ln Tv, ln rho, Y_1..Y_ns) (n_in = ns + 3), standardised
+ * x = (x_raw - mu) / sigma; targets t = asinh(tau0 J_C) with J_C row-major
+ * (s, r) (n_out = ns^2) and tau0 = 1 / the geometric mean of the non-zero
+ * |J_C| of the training set; the network's J_C is sinh(y) / tau0.
+ * All pointers below not marked host are device pointers owned by the caller;
+ * `work` is caller-owned device scratch of at least the size csi_mlp_sizes
+ * reports, 256-byte aligned.  Errors: CSI_ERR_ARG for sizes out of range or a
+ * short work buffer; CSI_ERR_HIP for launch failures. */
+
+/* number of FP32 master parameters and the work bytes the calls below need
+ * for up to `batch` samples per call (host outputs) */
+int csi_mlp_sizes(int n_in, int n_out, int batch, int *n_params, size_t *work_bytes);
+/* Training-set statistics and transforms: scales_host[2 n_in + 1] =
+ * (mu, sigma, tau0) from x_raw [n][n_in] and jc [n][n_out] (sigma = 1 for a
+ * feature with standard deviation < 1e-12); x [n][n_in] and t [n][n_out]
+ * receive the standardised features and targets. */
+int csi_mlp_prepare(csi_ctx *ctx, int n, int n_in, int n_out, const float *x_raw, const float *jc, float *x,
+                    float *t, double *scales_host, void *work, size_t work_bytes);
+/* y [n][n_out] = network(x [n][n_in]) with the BF16 path above */
+int csi_mlp_forward(csi_ctx *ctx, int n_in, int n_out, int n, const float *params, const float *x, float *y,
+                    void *work, size_t work_bytes);
+
+typedef struct {
+  int n_in, n_out;
+  int n_data;        /* rows of x and t */
+  int batch;         /* samples in this call, >= 1 */
+  const float *x;    /* [n_data][n_in] standardised features */
+  const float *t;    /* [n_data][n_out] targets */
+  const int *idx;    /* [batch] rows of this batch (entries outside [0, n_data) are skipped) */
+  float *params;     /* [n_params] FP32 master parameters */
+  void *work;
+  size_t work_bytes;
+} csi_mlp_batch;
+typedef struct { double lr, beta1, beta2, eps; } csi_adam;
+
+/* Mean squared error over the batch's samples and outputs (loss, host,
+ * nullable) and its gradient (grad [n_params], FP32) with respect to params. */
+int csi_mlp_grad(csi_ctx *ctx, const csi_mlp_batch *b, float *grad, double *loss);
+/* One training step: the gradient as above, then a bias-corrected Adam update
+ * of params and of the moments m, v [n_params] (step counts from 1). */
+int csi_mlp_train_step(csi_ctx *ctx, const csi_mlp_batch *b, float *m, float *v, int step, const csi_adam *h,
+                       double *loss);
+
+/* Training samples from the bound state: for cells 0..n-1 (n = min(N,
+ * max_samples), returned in *n_written) the raw features x_raw [n][ns + 3] and
+ * the exact J_C [n][ns * ns] (FP32). */
+int csi_sample_jacobians(csi_ctx *ctx, int max_samples, float *x_raw, float *jc, int *n_written);
+/* Install a trained network for CSI_JAC_SURROGATE (split form only):
+ * params [n_params] (device, copied into the workspace), scales (host,
+ * [2 n_in + 1] as from csi_mlp_prepare), n_in = ns + 3, n_out = ns^2.  Per
+ * cell and iteration the surrogate block is used when D_C = dC I - V J_C is
+ * strictly row diagonally dominant with a positive diagonal in molar units
+ * (D_rr M_r > sum_{c != r} |D_rc| M_c), else the exact J_C; and in
+ * csi_step, once stall_window iterations have run with it, the
+ * first iteration whose density residual exceeds stall_ratio times the one
+ * stall_window iterations earlier switches it off for the rest of the call. */
+int csi_set_surrogate(csi_ctx *ctx, const float *params, const double *scales, int n_in, int n_out,
+                      double stall_ratio, int stall_window);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsi.so")
 SPECIES = tuple(int(s) for s in os.environ.get("CSI_SPECIES", "2,3,5,11,20").split(","))
+# temperature models compiled per species count (the seeded 20-species mechanism is one-temperature)
+MODELS = {20: (1,)}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I" + CSRC, "-Wno-unused-result"]
@@ -31,14 +33,16 @@ def _stale(src, obj, deps):
     return any(os.path.getmtime(d) > t for d in [src, *deps])
 
 
-def build(jobs: int = 6, verbose: bool = False, force: bool = True) -> str:
+def build(jobs: int = 8, verbose: bool = False, force: bool = True) -> str:
     """Compile every unit (force=True) or only the stale ones, then link."""
     os.makedirs(BUILD, exist_ok=True)
     with open(os.path.join(BUILD, "species.txt"), "w") as f:
         f.write(",".join(map(str, SPECIES)))
     units = [(os.path.join(CSRC, "csi_api.hip"), os.path.join(BUILD, "csi_api.o"), [])]
     for ns in SPECIES:
-        units.append((os.path.join(CSRC, "csi_inst.hip"), os.path.join(BUILD, f"csi_inst_{ns}.o"), [f"-DCSI_NS={ns}"]))
+        for nt in MODELS.get(ns, (1, 2)):
+            units.append((os.path.join(CSRC, "csi_inst.hip"), os.path.join(BUILD, f"csi_inst_{ns}_{nt}.o"),
+                          [f"-DCSI_NS={ns}", f"-DCSI_NT={nt}"]))
     extra = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip") and f not in ("csi_api.hip", "csi_inst.hip"))
     for f in extra:
         units.append((os.path.join(CSRC, f), os.path.join(BUILD, f[:-4] + ".o"), []))

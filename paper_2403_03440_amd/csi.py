@@ -29,8 +29,9 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_set_freestream", "csi_workspace_bytes", "csi_bind_workspace", "csi_set_state", "csi_get_state",
             "csi_residual", "csi_implicit_op", "csi_consistency_correct", "csi_step", "csi_wall_heat_flux",
             "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times",
-            "csi_set_sweep"]
-PHASES = ["prim", "faces", "cell", "norms", "sweeps", "update"]
+            "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
+            "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate"]
+PHASES = ["prim", "faces", "cell", "norms", "sweep_fwd", "sweep_bwd", "update"]
 
 
 class CsiError(RuntimeError):
@@ -55,7 +56,18 @@ class StepParams(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("it_conv", C.c_int), ("n_clipped", C.c_int),
-                ("bad_cell", C.c_int), ("r0", C.c_double), ("r_last", C.c_double)]
+                ("bad_cell", C.c_int), ("r0", C.c_double), ("r_last", C.c_double),
+                ("n_dd_fallback", C.c_longlong), ("surrogate_off_at", C.c_int)]
+
+
+class MlpBatch(C.Structure):
+    _fields_ = [("n_in", C.c_int), ("n_out", C.c_int), ("n_data", C.c_int), ("batch", C.c_int),
+                ("x", C.c_void_p), ("t", C.c_void_p), ("idx", C.c_void_p), ("params", C.c_void_p),
+                ("work", C.c_void_p), ("work_bytes", C.c_size_t)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
 
 
 _lib = None
@@ -209,7 +221,7 @@ class Solver:
         N = self.N
         mode = self.last_mode if mode is None else mode
         shapes = {"R": (m.nv, N), "dtau": (N,), "src": (m.nv, N), "qw": (self.ni,), "T": (N,), "Tv": (N,),
-                  "p": (N,), "c": (N,)}
+                  "p": (N,), "c": (N,), "Jsur": (m.ns * m.ns, N)}
         if name in ("b", "dqs", "dq"):
             shape = (self.nsol(mode), N)
         elif name == "Dinv":
@@ -237,10 +249,108 @@ class Solver:
         self._check(self.L.csi_set_timing(self.ctx, int(on)))
 
     def phase_times(self, reset=False):
-        ms = np.zeros(7)
+        ms = np.zeros(len(PHASES) + 1)
         self._check(self.L.csi_phase_times(self.ctx, ms.ctypes.data_as(_dp), int(reset)))
-        n = max(ms[6], 1.0)
-        return {k: {"ms": float(ms[i]), "ms_per_iter": float(ms[i] / n)} for i, k in enumerate(PHASES)}
+        n = max(ms[-1], 1.0)
+        out = {k: {"ms": float(ms[i]), "ms_per_iter": float(ms[i] / n)} for i, k in enumerate(PHASES)}
+        out["iters"] = int(ms[-1])
+        return out
+
+    # ---------------------------------------------------------- surrogate
+    def sample_jacobians(self, x_raw, jc, max_samples=None):
+        """Features [n][ns+3] and exact J_C [n][ns*ns] (float32 cuda tensors) of
+        cells 0..n-1 of the current state; returns n."""
+        n = C.c_int(0)
+        ms = self.N if max_samples is None else max_samples
+        self._check(self.L.csi_sample_jacobians(self.ctx, ms, C.c_void_p(x_raw.data_ptr()),
+                                                C.c_void_p(jc.data_ptr()), C.byref(n)))
+        return n.value
+
+    def set_surrogate(self, params, scales, stall_ratio=0.98, stall_window=100):
+        """Install a network: params float32 cuda tensor, scales (mu, sigma, tau0) host."""
+        sa, sp = _d(scales)
+        ns = self.mech.ns
+        self._check(self.L.csi_set_surrogate(self.ctx, C.c_void_p(params.data_ptr()), sp, ns + 3, ns * ns,
+                                             C.c_double(stall_ratio), stall_window))
 
     def synchronize(self):
         self.torch.cuda.synchronize(self.dev)
+
+
+class Mlp:
+    """The surrogate network's kernels (hidden width 64) on one stream: data
+    preparation, inference, gradient and Adam training steps.  Tensors are
+    cuda tensors owned by the caller; the work buffer is allocated here with
+    torch for up to `batch` samples per call."""
+
+    def __init__(self, n_in, n_out, batch=4096, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.n_in, self.n_out, self.batch = n_in, n_out, batch
+        self.dev = torch.device("cuda", device)
+        st = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.ctx = C.c_void_p()
+        rc = self.L.csi_create(C.byref(self.ctx), device, C.c_void_p(st.cuda_stream))
+        if rc:
+            raise CsiError(rc, "csi_create")
+        npar, wb = C.c_int(0), C.c_size_t(0)
+        rc = self.L.csi_mlp_sizes(n_in, n_out, batch, C.byref(npar), C.byref(wb))
+        if rc:
+            raise CsiError(rc, "csi_mlp_sizes")
+        self.n_params = npar.value
+        self.work = torch.empty(wb.value, dtype=torch.uint8, device=self.dev)
+
+    def __del__(self):
+        try:
+            self.L.csi_destroy(self.ctx)
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CsiError(rc, self.L.csi_last_error(self.ctx).decode())
+
+    def _w(self):
+        return C.c_void_p(self.work.data_ptr()), C.c_size_t(self.work.numel())
+
+    @staticmethod
+    def _p(t):
+        return C.c_void_p(t.data_ptr())
+
+    def prepare(self, x_raw, jc):
+        """Standardised features, asinh targets and the scales (mu, sigma, tau0)."""
+        n = x_raw.shape[0]
+        x = self.torch.empty_like(x_raw)
+        t = self.torch.empty_like(jc)
+        scales = np.zeros(2 * self.n_in + 1)
+        self._check(self.L.csi_mlp_prepare(self.ctx, n, self.n_in, self.n_out, self._p(x_raw), self._p(jc),
+                                           self._p(x), self._p(t), scales.ctypes.data_as(_dp), *self._w()))
+        return x, t, scales
+
+    def forward(self, params, x):
+        y = self.torch.empty((x.shape[0], self.n_out), dtype=self.torch.float32, device=self.dev)
+        self._check(self.L.csi_mlp_forward(self.ctx, self.n_in, self.n_out, x.shape[0], self._p(params),
+                                           self._p(x), self._p(y), *self._w()))
+        return y
+
+    def _batch(self, params, x, t, idx):
+        w, wb = self._w()
+        return MlpBatch(self.n_in, self.n_out, x.shape[0], idx.shape[0], self._p(x).value, self._p(t).value,
+                        self._p(idx).value, self._p(params).value, w.value, wb.value)
+
+    def grad(self, params, x, t, idx):
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.dev)
+        loss = C.c_double(0)
+        b = self._batch(params, x, t, idx)
+        self._check(self.L.csi_mlp_grad(self.ctx, C.byref(b), self._p(g), C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, params, m, v, x, t, idx, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   want_loss=True):
+        b = self._batch(params, x, t, idx)
+        h = Adam(lr, beta1, beta2, eps)
+        loss = C.c_double(0)
+        self._check(self.L.csi_mlp_train_step(self.ctx, C.byref(b), self._p(m), self._p(v), step, C.byref(h),
+                                              C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None

@@ -9,27 +9,33 @@
 
 #include "../../include/csi.h"
 #include "csi_mech.hpp"
+#include "csi_mlp.hpp"
 #include "csi_runner.hpp"
 
 using namespace csi;
 
-// per-species-count factories (weak: a build may compile a subset)
-__attribute__((weak)) csi::IRunner *csi_make_runner_2(int);
-__attribute__((weak)) csi::IRunner *csi_make_runner_3(int);
-__attribute__((weak)) csi::IRunner *csi_make_runner_5(int);
-__attribute__((weak)) csi::IRunner *csi_make_runner_11(int);
-__attribute__((weak)) csi::IRunner *csi_make_runner_20(int);
+// per-(species count, temperature model) factories; weak, so that a build may
+// compile a subset (the 20-species mechanism is built for one temperature)
+#define CSI_WEAK_FACTORY(ns, nt) __attribute__((weak)) csi::IRunner *csi_make_runner_##ns##_##nt();
+CSI_WEAK_FACTORY(2, 1) CSI_WEAK_FACTORY(2, 2) CSI_WEAK_FACTORY(3, 1) CSI_WEAK_FACTORY(3, 2)
+CSI_WEAK_FACTORY(5, 1) CSI_WEAK_FACTORY(5, 2) CSI_WEAK_FACTORY(11, 1) CSI_WEAK_FACTORY(11, 2)
+CSI_WEAK_FACTORY(20, 1) CSI_WEAK_FACTORY(20, 2)
 
 namespace csi {
 IRunner *make_runner(int ns, int nt) {
+#define CSI_PICK(n)                                                                  \
+  case n:                                                                            \
+    if (nt == 1) return csi_make_runner_##n##_1 ? csi_make_runner_##n##_1() : nullptr; \
+    return csi_make_runner_##n##_2 ? csi_make_runner_##n##_2() : nullptr;
   switch (ns) {
-    case 2: return csi_make_runner_2 ? csi_make_runner_2(nt) : nullptr;
-    case 3: return csi_make_runner_3 ? csi_make_runner_3(nt) : nullptr;
-    case 5: return csi_make_runner_5 ? csi_make_runner_5(nt) : nullptr;
-    case 11: return csi_make_runner_11 ? csi_make_runner_11(nt) : nullptr;
-    case 20: return csi_make_runner_20 ? csi_make_runner_20(nt) : nullptr;
+    CSI_PICK(2)
+    CSI_PICK(3)
+    CSI_PICK(5)
+    CSI_PICK(11)
+    CSI_PICK(20)
     default: return nullptr;
   }
+#undef CSI_PICK
 }
 }  // namespace csi
 
@@ -49,6 +55,10 @@ struct csi_ctx {
   bool has_grid = false, has_mech = false, has_fs = false, bound = false, has_state = false, has_res = false;
   int last_mode = -1, last_prec = -1;
   bool has_dq = false;
+  // installed surrogate network (inside the workspace)
+  bool has_sur = false;
+  double sur_ratio = 0.98;
+  int sur_window = 100;
   // workspace
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -60,7 +70,7 @@ struct csi_ctx {
   // phase timing (HIP events, created on first use)
   bool timing = false;
   std::vector<hipEvent_t> ev;
-  double phase_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   int nv() const { return ns + 3 + (nt == 2 ? 1 : 0); }
   int nf() const { return nt == 2 ? 5 : 4; }
@@ -79,7 +89,7 @@ int hip_check(csi_ctx *c, hipError_t e, const char *what) {
 }
 
 struct Layout {
-  size_t off[40];
+  size_t off[48];
   size_t total;
 };
 
@@ -99,6 +109,7 @@ Layout layout(const csi_ctx *c, int nprim) {
   const StripMap sm = strip_map(c->ni, c->nj, 16), sm64 = strip_map(c->ni, c->nj, 64);
   const size_t A = std::max<size_t>(N, std::max<size_t>(sm.LEN, sm64.LEN));
   const size_t nstrip = std::max(sm.nstrip, sm64.nstrip);
+  const MlpDims sd = mlp_dims(c->ns + 3, c->ns * c->ns);
   size_t sizes[] = {
       sizeof(Mech),                       // 0 mech
       N * 8, N * 8, N * 8, NN * 8, NN * 8, // 1-5 V xc yc xn yn
@@ -118,7 +129,11 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(6 + 2 * c->ns) * A * 8,                  // 32 strip state records
       size_t(16) * A * 8,                             // 33 strip face records
       size_t(nstrip) * c->nj * nsol * 8,              // 34 strip-boundary pushes
-      size_t(2 * nstrip + 2) * 4,                     // 35 strip progress counters and tickets
+      size_t(strip_sync_ints(int(nstrip))) * 4,       // 35 strip progress counters and tickets (two parts)
+      size_t(c->ns) * c->ns * N * 4,                  // 36 surrogate J_C
+      size_t(sd.nslots) * 16,                         // 37 surrogate packed operands
+      size_t(sd.np) * 4,                              // 38 surrogate FP32 parameters
+      size_t(2 * sd.n_in + 1) * 8,                    // 39 surrogate scales
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -174,7 +189,7 @@ int read_flags(csi_ctx *c, int *fl) {
 }
 
 int reset_flags(csi_ctx *c) {
-  int fl[FL_N] = {INT_MAX, 0, -1, 0, INT_MAX, 0, 0, 0};
+  int fl[FL_N] = {INT_MAX, 0, -1, 0, INT_MAX, 0, -1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int rc = hip_check(c, hipMemcpyAsync(c->w.flags, fl, sizeof(fl), hipMemcpyHostToDevice, c->stream), "flags");
   if (rc) return rc;
   return hip_check(c, hipStreamSynchronize(c->stream), "sync");
@@ -222,7 +237,9 @@ int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
   if (!c || !mm) return CSI_ERR_ARG;
   if (mm->ns < 2 || mm->ns > MAXS || mm->nr < 0 || mm->nr > MAXR) return c->fail(CSI_ERR_ARG, "set_mechanism: sizes");
   IRunner *r = make_runner(mm->ns, mm->two_temp ? 2 : 1);
-  if (!r) return c->fail(CSI_ERR_UNSUPPORTED, "no kernels compiled for ns = " + std::to_string(mm->ns));
+  if (!r)
+    return c->fail(CSI_ERR_UNSUPPORTED, "no kernels compiled for ns = " + std::to_string(mm->ns) +
+                                            (mm->two_temp ? " with two temperatures" : " with one temperature"));
   std::string err;
   if (!build_mech(mm, c->mech, err)) { delete r; return c->fail(CSI_ERR_ARG, "set_mechanism: " + err); }
   delete c->run;
@@ -283,6 +300,11 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.face = b + L.off[33];
   w.bnd = b + L.off[34];
   w.sync = reinterpret_cast<int *>(b + L.off[35]);
+  w.sur.J = reinterpret_cast<float *>(b + L.off[36]);
+  w.sur.P = reinterpret_cast<const u16x8 *>(b + L.off[37]);
+  w.sur.p = reinterpret_cast<const float *>(b + L.off[38]);
+  w.sur.scales = reinterpret_cast<const double *>(b + L.off[39]);
+  c->has_sur = false;
   w.strip_w = c->strip_w;
   w.pub_every = c->pub_every;
   w.spin_limit = 4000000;
@@ -372,9 +394,13 @@ int csi_implicit_op(csi_ctx *c, int mode, int precision, int jac) {
   if (!c) return CSI_ERR_ARG;
   if (mode != CSI_COUPLED && mode != CSI_SPLIT) return c->fail(CSI_ERR_ARG, "mode");
   if (precision != CSI_FP64 && precision != CSI_MIXED) return c->fail(CSI_ERR_ARG, "precision");
-  if (jac != CSI_JAC_EXACT) return c->fail(CSI_ERR_UNSUPPORTED, "surrogate Jacobian not installed");
+  if (jac != CSI_JAC_EXACT && jac != CSI_JAC_SURROGATE) return c->fail(CSI_ERR_ARG, "jac");
+  if (jac == CSI_JAC_SURROGATE && mode != CSI_SPLIT) return c->fail(CSI_ERR_ARG, "the surrogate serves the split form");
+  if (jac == CSI_JAC_SURROGATE && !c->has_sur) return c->fail(CSI_ERR_STATE, "no surrogate installed");
   if (!ready(c) || !c->has_res) return c->fail(CSI_ERR_STATE, "implicit_op before residual");
-  hipError_t e = c->run->cell(c->g, c->w, c->stream, 0.0, mode, precision, 2, false);
+  hipError_t e = hipSuccess;
+  if (jac == CSI_JAC_SURROGATE) e = c->run->surrogate(c->g, c->w, c->stream, false);
+  if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, 0.0, mode, precision, jac == CSI_JAC_SURROGATE ? 6 : 2, false);
   if (e == hipSuccess) e = c->run->sweeps(c->g, c->w, c->stream, mode, precision, false);
   int rc = hip_check(c, e, "implicit_op launch");
   if (rc) return rc;
@@ -406,6 +432,9 @@ int csi_consistency_correct(csi_ctx *c, int kind) {
   return CSI_OK;
 }
 
+// events per timed iteration: boundaries of prim, faces, cell, norms, forward sweep, backward sweep, update
+static constexpr int NEV = 8;
+
 int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   if (!c || !p) return CSI_ERR_ARG;
   if (!ready(c)) return c->fail(CSI_ERR_STATE, "step: workspace/state not set");
@@ -414,13 +443,17 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     return c->fail(CSI_ERR_ARG, "step: bad parameters");
   if ((p->mode == CSI_COUPLED && p->kind != CSI_CLOSURE) || (p->mode == CSI_SPLIT && p->kind != CSI_CC1 && p->kind != CSI_CC2))
     return c->fail(CSI_ERR_ARG, "step: correction kind does not match mode");
-  if (p->jac != CSI_JAC_EXACT) return c->fail(CSI_ERR_UNSUPPORTED, "surrogate Jacobian not installed");
+  if (p->jac != CSI_JAC_EXACT && p->jac != CSI_JAC_SURROGATE) return c->fail(CSI_ERR_ARG, "step: jac");
+  const bool sur = p->jac == CSI_JAC_SURROGATE;
+  if (sur && p->mode != CSI_SPLIT) return c->fail(CSI_ERR_ARG, "step: the surrogate serves the split form");
+  if (sur && !c->has_sur) return c->fail(CSI_ERR_STATE, "step: no surrogate installed");
   int rc = reset_flags(c);
   if (rc) return rc;
   int every = p->check_every > 0 ? p->check_every : 50;
   csi_step_stats st{};
   st.bad_cell = -1;
   st.it_conv = -1;
+  st.surrogate_off_at = -1;
   int fl[FL_N];
   const long it_start = c->it_global;
   for (int it = 0; it < p->max_iter; ++it) {
@@ -428,10 +461,10 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     double cfl = p->cfl_ramp > 0 ? std::pow(p->cfl, double(std::min<long>(m, p->cfl_ramp)) / p->cfl_ramp) : p->cfl;
     hipEvent_t *E = nullptr;
     if (c->timing) {
-      size_t slot = size_t(it % every) * 7;
-      if (c->ev.size() < slot + 7) {
+      size_t slot = size_t(it % every) * NEV;
+      if (c->ev.size() < slot + NEV) {
         size_t old_n = c->ev.size();
-        c->ev.resize(size_t(every) * 7 > slot + 7 ? size_t(every) * 7 : slot + 7);
+        c->ev.resize(size_t(every) * NEV > slot + NEV ? size_t(every) * NEV : slot + NEV);
         for (size_t k = old_n; k < c->ev.size(); ++k)
           if ((rc = hip_check(c, hipEventCreate(&c->ev[k]), "event"))) return rc;
       }
@@ -443,14 +476,16 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     if (E && e == hipSuccess) e = hipEventRecord(E[1], c->stream);
     if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[2], c->stream);
-    if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, 3, true);
+    if (sur && e == hipSuccess) e = c->run->surrogate(c->g, c->w, c->stream, true);
+    if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, sur ? 7 : 3, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[3], c->stream);
-    if (e == hipSuccess) e = c->run->norms(c->w, c->stream, int(m), p->tol, true);
+    const StallArgs stall{sur ? c->w.flags + FL_SURR_OFF : nullptr, int(it_start), c->sur_window, c->sur_ratio};
+    if (e == hipSuccess) e = c->run->norms(c->w, c->stream, int(m), p->tol, true, stall);
     if (E && e == hipSuccess) e = hipEventRecord(E[4], c->stream);
-    if (e == hipSuccess) e = c->run->sweeps(c->g, c->w, c->stream, p->mode, p->precision, true);
-    if (E && e == hipSuccess) e = hipEventRecord(E[5], c->stream);
-    if (e == hipSuccess) e = c->run->update(c->g, c->w, c->stream, p->mode, p->precision, p->kind, true);
+    if (e == hipSuccess) e = c->run->sweeps(c->g, c->w, c->stream, p->mode, p->precision, true, E ? E[5] : nullptr);
     if (E && e == hipSuccess) e = hipEventRecord(E[6], c->stream);
+    if (e == hipSuccess) e = c->run->update(c->g, c->w, c->stream, p->mode, p->precision, p->kind, true);
+    if (E && e == hipSuccess) e = hipEventRecord(E[7], c->stream);
     if ((rc = hip_check(c, e, "step launch"))) return rc;
     c->it_global++;
     st.iters = it + 1;
@@ -459,12 +494,12 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
       if (c->timing) {
         int nb_ = (it % every) + 1;
         for (int b = 0; b < nb_; ++b) {
-          for (int ph = 0; ph < 6; ++ph) {
+          for (int ph = 0; ph < NEV - 1; ++ph) {
             float msf = 0.f;
-            if (hipEventElapsedTime(&msf, c->ev[size_t(b) * 7 + ph], c->ev[size_t(b) * 7 + ph + 1]) == hipSuccess)
+            if (hipEventElapsedTime(&msf, c->ev[size_t(b) * NEV + ph], c->ev[size_t(b) * NEV + ph + 1]) == hipSuccess)
               c->phase_ms[ph] += msf;
           }
-          c->phase_ms[6] += 1.0;
+          c->phase_ms[NEV - 1] += 1.0;
         }
       }
       if (fl[FL_ABORT]) {
@@ -491,6 +526,12 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   }
   if ((rc = read_flags(c, fl))) return rc;
   st.n_clipped = fl[FL_CLIP];
+  {
+    unsigned long long dd;
+    std::memcpy(&dd, fl + FL_DDFAIL, sizeof(dd));
+    st.n_dd_fallback = (long long)dd;
+  }
+  st.surrogate_off_at = fl[FL_SURR_OFF];
   double nrm[2] = {0, 0}, r0 = 0;
   (void)hipMemcpy(nrm, c->w.norms, 16, hipMemcpyDeviceToHost);
   (void)hipMemcpy(&r0, c->w.r0, 8, hipMemcpyDeviceToHost);
@@ -583,6 +624,14 @@ int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
   else if (n == "Dinv") {
     rsrc = c->w.Dinv;
     cnt = (c->last_mode == CSI_COUPLED ? size_t(c->nb()) * c->nb() : 6 + size_t(c->ns) * c->ns) * N;
+  } else if (n == "Jsur") {
+    const size_t cntj = size_t(c->ns) * c->ns * N;
+    if (count < cntj) return c->fail(CSI_ERR_ARG, "buffer too small for Jsur");
+    std::vector<float> tmp(cntj);
+    int rc = hip_check(c, hipMemcpy(tmp.data(), c->w.sur.J, cntj * 4, hipMemcpyDeviceToHost), "get");
+    if (rc) return rc;
+    for (size_t k = 0; k < cntj; ++k) out[k] = tmp[k];
+    return CSI_OK;
   } else if (n == "T" || n == "Tv" || n == "p" || n == "c") {
     int fld = n == "T" ? F_T : n == "Tv" ? F_TV : n == "p" ? F_P : F_C;
     std::vector<double> tmp(NP);
@@ -606,17 +655,213 @@ int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
     stride = sm.LEN;
   }
   const size_t esz = c->last_prec == CSI_MIXED ? 4 : 8;
-  std::vector<char> tmp(rows * stride * esz);
+  // array width (fields per record) of the step-blocked layout
+  const int F = n == "Dinv" ? std::max(c->nb() * c->nb(), 6 + c->ns * c->ns) : c->nsplit();
+  std::vector<char> tmp(size_t(F) * stride * esz);
   int rc = hip_check(c, hipMemcpy(tmp.data(), rsrc, tmp.size(), hipMemcpyDeviceToHost), "get");
   if (rc) return rc;
   for (size_t r_ = 0; r_ < rows; ++r_)
     for (int j = 0; j < c->nj; ++j)
       for (int i = 0; i < c->ni; ++i) {
-        size_t pos = c->strip_w > 0 ? size_t(strip_pos(sm, i, j)) : size_t(j) * c->ni + i;
-        size_t k = r_ * stride + pos;
+        size_t k = c->strip_w > 0 ? size_t(rec_idx(strip_pos(sm, i, j), i % c->strip_w, F, int(r_), c->strip_w))
+                                  : r_ * stride + size_t(j) * c->ni + i;
         out[r_ * N + size_t(j) * c->ni + i] =
             esz == 4 ? double(reinterpret_cast<const float *>(tmp.data())[k]) : reinterpret_cast<const double *>(tmp.data())[k];
       }
+  return CSI_OK;
+}
+
+
+// ------------------------------------------------------------ surrogate network
+}  // extern "C"
+
+namespace {
+
+struct MlpWork {
+  size_t off[7];
+  size_t total;
+};
+
+// scratch of the network calls: packed operands, gradient partials, loss
+// partials, loss, statistics partials, scales
+MlpWork mlp_work(const MlpDims &d, int batch) {
+  MlpWork W;
+  const size_t nblk = (size_t(batch) + 63) / 64;
+  size_t sizes[] = {size_t(d.nslots) * 16, nblk * d.np * 4, nblk * 8, 8,
+                    size_t(MLP_MAX_IN) * MLP_PREP_BLOCKS * 8, 2 * size_t(MLP_PREP_BLOCKS) * 8,
+                    size_t(2 * MLP_MAX_IN + 1) * 8};
+  size_t o = 0;
+  for (int k = 0; k < 7; ++k) { W.off[k] = o; o += al(sizes[k]); }
+  W.total = o;
+  return W;
+}
+
+bool mlp_ok(int n_in, int n_out) { return n_in >= 1 && n_in <= MLP_MAX_IN && n_out >= 1 && n_out <= MLP_MAX_OUT; }
+
+int mlp_check_work(csi_ctx *c, const MlpDims &d, int batch, const void *work, size_t bytes) {
+  if (!work || reinterpret_cast<uintptr_t>(work) % 256) return c->fail(CSI_ERR_ARG, "work buffer missing or not 256-byte aligned");
+  if (bytes < mlp_work(d, batch).total) return c->fail(CSI_ERR_ARG, "work buffer too small");
+  return CSI_OK;
+}
+
+hipError_t mlp_pack(const MlpDims &d, const float *params, void *P, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((d.nslots + 255) / 256), dim3(256), 0, st, d, params, static_cast<u16x8 *>(P));
+  return hipGetLastError();
+}
+
+// gradient partials for one batch, then the ordered reduction (and Adam when m, v are given)
+int mlp_grad_adam(csi_ctx *c, const csi_mlp_batch *b, float *grad, float *am, float *av, int step, const csi_adam *h,
+                  double *loss) {
+  if (!b || !b->x || !b->t || !b->idx || !b->params) return c->fail(CSI_ERR_ARG, "mlp batch: null pointer");
+  if (!mlp_ok(b->n_in, b->n_out) || b->batch < 1 || b->n_data < 1) return c->fail(CSI_ERR_ARG, "mlp batch: sizes");
+  const MlpDims d = mlp_dims(b->n_in, b->n_out);
+  int rc = mlp_check_work(c, d, b->batch, b->work, b->work_bytes);
+  if (rc) return rc;
+  const MlpWork W = mlp_work(d, b->batch);
+  char *w = static_cast<char *>(b->work);
+  auto *P = reinterpret_cast<const u16x8 *>(w + W.off[0]);
+  auto *part = reinterpret_cast<float *>(w + W.off[1]);
+  auto *lpart = reinterpret_cast<double *>(w + W.off[2]);
+  auto *ldev = reinterpret_cast<double *>(w + W.off[3]);
+  const int nblk = (b->batch + 63) / 64;
+  const float scale = float(2.0 / (double(b->batch) * b->n_out));
+  hipError_t e = mlp_pack(d, b->params, w + W.off[0], c->stream);
+  if (e == hipSuccess) {
+    if (d.ks1 == 1)
+      hipLaunchKernelGGL(k_mlp_grad<1>, dim3(nblk), dim3(256), 0, c->stream, d, P, b->params, b->x, b->t, b->idx,
+                         b->batch, b->n_data, scale, part, lpart);
+    else
+      hipLaunchKernelGGL(k_mlp_grad<2>, dim3(nblk), dim3(256), 0, c->stream, d, P, b->params, b->x, b->t, b->idx,
+                         b->batch, b->n_data, scale, part, lpart);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    const double lr = h ? h->lr : 0.0, b1 = h ? h->beta1 : 0.0, b2 = h ? h->beta2 : 0.0, eps = h ? h->eps : 0.0;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((d.np + 255) / 256), dim3(256), 0, c->stream, d.np, nblk, part, lpart,
+                       1.0 / (double(b->batch) * b->n_out), ldev, grad, am ? b->params : nullptr, am, av, step, lr, b1,
+                       b2, eps);
+    e = hipGetLastError();
+  }
+  if ((rc = hip_check(c, e, "mlp launch"))) return rc;
+  if (loss) {
+    if ((rc = hip_check(c, hipMemcpyAsync(loss, ldev, 8, hipMemcpyDeviceToHost, c->stream), "loss"))) return rc;
+    return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  }
+  return CSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int csi_mlp_sizes(int n_in, int n_out, int batch, int *n_params, size_t *work_bytes) {
+  if (!mlp_ok(n_in, n_out) || batch < 1) return CSI_ERR_ARG;
+  const MlpDims d = mlp_dims(n_in, n_out);
+  if (n_params) *n_params = d.np;
+  if (work_bytes) *work_bytes = mlp_work(d, batch).total;
+  return CSI_OK;
+}
+
+int csi_mlp_prepare(csi_ctx *c, int n, int n_in, int n_out, const float *x_raw, const float *jc, float *x, float *t,
+                    double *scales_host, void *work, size_t work_bytes) {
+  if (!c) return CSI_ERR_ARG;
+  if (!mlp_ok(n_in, n_out) || n < 1 || !x_raw || !jc || !x || !t || !scales_host)
+    return c->fail(CSI_ERR_ARG, "mlp_prepare: arguments");
+  const MlpDims d = mlp_dims(n_in, n_out);
+  int rc = mlp_check_work(c, d, 1, work, work_bytes);
+  if (rc) return rc;
+  const MlpWork W = mlp_work(d, 1);
+  char *w = static_cast<char *>(work);
+  auto *mpart = reinterpret_cast<double *>(w + W.off[4]);
+  auto *jpart = reinterpret_cast<double *>(w + W.off[5]);
+  auto *sc = reinterpret_cast<double *>(w + W.off[6]);
+  hipStream_t st = c->stream;
+  const dim3 gm(MLP_PREP_BLOCKS, n_in);
+  hipLaunchKernelGGL(k_prep_moments, gm, dim3(256), 0, st, n, n_in, x_raw, nullptr, mpart);
+  hipLaunchKernelGGL(k_prep_logj, dim3(MLP_PREP_BLOCKS), dim3(256), 0, st, long(n) * n_out, jc, jpart);
+  hipLaunchKernelGGL(k_prep_finish, dim3(1), dim3(64), 0, st, 0, n, n_in, mpart, jpart, sc);
+  hipLaunchKernelGGL(k_prep_moments, gm, dim3(256), 0, st, n, n_in, x_raw, sc, mpart);
+  hipLaunchKernelGGL(k_prep_finish, dim3(1), dim3(64), 0, st, 1, n, n_in, mpart, jpart, sc);
+  const long tot = long(n) * (n_in > n_out ? n_in : n_out);
+  hipLaunchKernelGGL(k_prep_apply, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, long(n), n_in, n_out, x_raw, jc,
+                     sc, x, t);
+  if ((rc = hip_check(c, hipGetLastError(), "mlp_prepare launch"))) return rc;
+  if ((rc = hip_check(c, hipMemcpyAsync(scales_host, sc, size_t(2 * n_in + 1) * 8, hipMemcpyDeviceToHost, st), "scales")))
+    return rc;
+  return hip_check(c, hipStreamSynchronize(st), "sync");
+}
+
+int csi_mlp_forward(csi_ctx *c, int n_in, int n_out, int n, const float *params, const float *x, float *y, void *work,
+                    size_t work_bytes) {
+  if (!c) return CSI_ERR_ARG;
+  if (!mlp_ok(n_in, n_out) || n < 1 || !params || !x || !y) return c->fail(CSI_ERR_ARG, "mlp_forward: arguments");
+  const MlpDims d = mlp_dims(n_in, n_out);
+  int rc = mlp_check_work(c, d, 1, work, work_bytes);
+  if (rc) return rc;
+  char *w = static_cast<char *>(work);
+  const MlpWork W = mlp_work(d, 1);
+  hipError_t e = mlp_pack(d, params, w + W.off[0], c->stream);
+  auto *P = reinterpret_cast<const u16x8 *>(w + W.off[0]);
+  const unsigned nb = unsigned((long(n) + 63) / 64);
+  if (e == hipSuccess) {
+    if (d.ks1 == 1) hipLaunchKernelGGL(k_mlp_forward<1>, dim3(nb), dim3(256), 0, c->stream, d, P, params, x, n, y);
+    else hipLaunchKernelGGL(k_mlp_forward<2>, dim3(nb), dim3(256), 0, c->stream, d, P, params, x, n, y);
+    e = hipGetLastError();
+  }
+  return hip_check(c, e, "mlp_forward launch");
+}
+
+int csi_mlp_grad(csi_ctx *c, const csi_mlp_batch *b, float *grad, double *loss) {
+  if (!c) return CSI_ERR_ARG;
+  if (!grad) return c->fail(CSI_ERR_ARG, "mlp_grad: null gradient");
+  return mlp_grad_adam(c, b, grad, nullptr, nullptr, 0, nullptr, loss);
+}
+
+int csi_mlp_train_step(csi_ctx *c, const csi_mlp_batch *b, float *m, float *v, int step, const csi_adam *h,
+                       double *loss) {
+  if (!c) return CSI_ERR_ARG;
+  if (!m || !v || !h || step < 1 || !(h->lr > 0.0) || !(h->beta1 >= 0.0 && h->beta1 < 1.0) ||
+      !(h->beta2 >= 0.0 && h->beta2 < 1.0) || !(h->eps > 0.0))
+    return c->fail(CSI_ERR_ARG, "mlp_train_step: Adam arguments");
+  return mlp_grad_adam(c, b, nullptr, m, v, step, h, loss);
+}
+
+int csi_sample_jacobians(csi_ctx *c, int max_samples, float *x_raw, float *jc, int *n_written) {
+  if (!c) return CSI_ERR_ARG;
+  if (max_samples < 1 || !x_raw || !jc) return c->fail(CSI_ERR_ARG, "sample_jacobians: arguments");
+  if (!ready(c)) return c->fail(CSI_ERR_STATE, "sample_jacobians: workspace/state not set");
+  const int n = max_samples < c->N ? max_samples : c->N;
+  int rc = hip_check(c, c->run->sample(c->g, c->w, c->stream, n, x_raw, jc), "sample launch");
+  if (rc) return rc;
+  int fl[FL_N];
+  if ((rc = read_flags(c, fl))) return rc;
+  if (fl[FL_BAD] != INT_MAX) return c->fail(CSI_ERR_NONFINITE, "non-physical state at cell " + std::to_string(fl[FL_BAD]));
+  if (n_written) *n_written = n;
+  c->has_res = false;
+  return CSI_OK;
+}
+
+int csi_set_surrogate(csi_ctx *c, const float *params, const double *scales, int n_in, int n_out, double stall_ratio,
+                      int stall_window) {
+  if (!c) return CSI_ERR_ARG;
+  if (!c->bound) return c->fail(CSI_ERR_STATE, "set_surrogate before bind_workspace");
+  if (!params || !scales || n_in != c->ns + 3 || n_out != c->ns * c->ns || !(stall_ratio > 0.0) || stall_window < 1)
+    return c->fail(CSI_ERR_ARG, "set_surrogate: expects n_in = ns + 3, n_out = ns^2, ratio > 0, window >= 1");
+  for (int k = 0; k < 2 * n_in + 1; ++k)
+    if (!std::isfinite(scales[k]) || (k >= n_in && !(scales[k] > 0.0)))
+      return c->fail(CSI_ERR_ARG, "set_surrogate: scales must be finite with positive sigma and tau0");
+  const MlpDims d = mlp_dims(n_in, n_out);
+  hipStream_t st = c->stream;
+  hipError_t e = hipMemcpyAsync(const_cast<float *>(c->w.sur.p), params, size_t(d.np) * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(const_cast<double *>(c->w.sur.scales), scales, size_t(2 * n_in + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = mlp_pack(d, c->w.sur.p, const_cast<u16x8 *>(c->w.sur.P), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  int rc = hip_check(c, e, "set_surrogate");
+  if (rc) return rc;
+  c->has_sur = true;
+  c->sur_ratio = stall_ratio;
+  c->sur_window = stall_window;
   return CSI_OK;
 }
 

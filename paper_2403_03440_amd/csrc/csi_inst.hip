@@ -1,13 +1,11 @@
-// Kernel instantiation for one species count (compiled once per CSI_NS).
+// Kernel instantiation for one species count and temperature model (compiled
+// once per (CSI_NS, CSI_NT)).
 #include "csi_runner.hpp"
 
-#ifndef CSI_NS
-#error "CSI_NS must be defined"
+#if !defined(CSI_NS) || !defined(CSI_NT)
+#error "CSI_NS and CSI_NT must be defined"
 #endif
-#define CSI_CAT2(a, b) a##b
-#define CSI_CAT(a, b) CSI_CAT2(a, b)
+#define CSI_CAT4(a, b, c, d) a##b##c##d
+#define CSI_FACTORY(ns, nt) CSI_CAT4(csi_make_runner_, ns, _, nt)
 
-csi::IRunner *CSI_CAT(csi_make_runner_, CSI_NS)(int nt) {
-  if (nt == 1) return new csi::Runner<CSI_NS, 1>();
-  return new csi::Runner<CSI_NS, 2>();
-}
+csi::IRunner *CSI_FACTORY(CSI_NS, CSI_NT)() { return new csi::Runner<CSI_NS, CSI_NT>(); }

@@ -381,6 +381,44 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
   return true;
 }
 
+// ------------------------------------------------ sweep record layout
+// Strip map of the persistent sweeps (one wavefront per strip of W columns;
+// at step d lane l owns cell (i0 + l, d - l)) and the step-blocked layout of
+// the per-cell sweep records: all cells of one strip step contiguous,
+// field-major inside the step,
+//   element (field f of F, strip s, step d, lane l) at ((s NSTEP + d) F + f) W + l.
+struct StripMap {
+  int W, NSTEP, nstrip;
+  long LEN;
+};
+
+__host__ __device__ inline StripMap strip_map(int ni, int nj, int W) {
+  StripMap s;
+  s.W = W;
+  s.NSTEP = nj + W - 1;
+  s.nstrip = (ni + W - 1) / W;
+  s.LEN = long(s.nstrip) * s.NSTEP * W;
+  return s;
+}
+// cell (i, j) -> step-major cell position (s NSTEP + d) W + l, d = j + l
+__host__ __device__ inline long strip_pos(const StripMap &sm, int i, int j) {
+  int s = i / sm.W, l = i - s * sm.W;
+  return (long(s) * sm.NSTEP + j + l) * sm.W + l;
+}
+// element of field f (of F) of the record at cell position pos (lane l)
+__host__ __device__ inline long rec_idx(long pos, int l, int F, int f, int W) {
+  return (pos - l) * F + long(f) * W + l;
+}
+
+// record field counts (array widths, the same for every mode)
+template <int NS, int NT> struct Rec {
+  using D = Dims<NS, NT>;
+  static constexpr int NSOL = D::nsplit;                       // b, xs, x
+  static constexpr int NDINV = (D::nb * D::nb > 6 + NS * NS) ? D::nb * D::nb : 6 + NS * NS;
+  static constexpr int NSTATE = 6 + 2 * NS;                    // u v H eve pE pv | Y[NS] pr[NS] (split: prY at 6)
+  static constexpr int NFACE = 16;                             // mE mN mW mS (x,y) | cE cN cW cS | cCE cCN cCW cCS
+};
+
 // ----------------------------------------------------------- cell kernel
 // Residual R = sum_f F_f S_f - V S(Q), local time step, norms partials,
 // chemistry and its Jacobian, the diagonal blocks (paper Section 2.2: I_m and
@@ -389,12 +427,15 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
 // mode 1: split (flow block in closed form, ns x ns species block)
 struct CellOut {
   double *R, *dtau, *part;     // part: per-block norm partials [2][nblocks]
-  void *Dinv;                  // coupled: [nb*nb][STR]; split: DF [6][STR] then DC [ns*ns][STR]
-  void *b;                     // RHS [nsol][STR]
+  void *Dinv;                  // coupled: nb*nb fields; split: DF 6 fields then DC ns*ns fields
+  void *b;                     // RHS, nsol fields
   void *state, *face;          // strip layout only: JVP state and face coefficients
   double *src;                 // optional source vector [nv][N] (debug)
   int *bad;
   int strip_w;                 // 0: cell-major layout (stride N); W > 0: strip layout of width W
+  const float *Jsur;           // surrogate J_C [ns * ns][N] (flags bit 4)
+  unsigned long long *ddfail;  // count of cells whose surrogate block failed the dominance check
+  const int *surr_off;         // >= 0: surrogate switched off (stall), use the exact block
 };
 
 template <int NS, int NT, typename RT>
@@ -427,7 +468,12 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     double T = prim[F_T * NP + pc], Tv = prim[F_TV * NP + pc], pp = prim[F_P * NP + pc];
     Chem<NS, NT> C;
     const bool do_res = flags & 1, do_diag = flags & 2;
-    if (do_diag) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
+    // surrogate species block (split form): in 1T the exact J_C is only
+    // needed by cells whose surrogate block fails the dominance check; in 2T
+    // the flow block's omega_ve row needs the exact derivatives anyway
+    const bool try_sur = do_diag && mode == 1 && (flags & 4) && out.Jsur && *out.surr_off < 0;
+    bool have_jac = do_diag && !(try_sur && NT == 1);
+    if (have_jac) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
     else chemistry<NS, NT, false>(m, rs, T, Tv, pp, C);
     double R[NV];
 #pragma unroll
@@ -473,12 +519,17 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     prim_from_q<NS, NT>(m, q, P);
     double Vdt = Vp / dt;
     RT *bb = reinterpret_cast<RT *>(out.b);
-    long STR = g.N, pos = p;
-    if (out.strip_w > 0) {
-      int W = out.strip_w, sidx = i / W, l = i - sidx * W, NSTEP = g.nj + W - 1, nstrip = (g.ni + W - 1) / W;
-      STR = long(nstrip) * NSTEP * W;
-      pos = (long(sidx) * NSTEP + j + l) * W + l;
+    // record element index: cell-major (field f at f N + p) or step-blocked strip layout
+    const int SWD = out.strip_w;
+    long spos = 0;
+    int sl = 0;
+    if (SWD > 0) {
+      const int sidx = i / SWD, NSTEP = g.nj + SWD - 1;
+      sl = i - sidx * SWD;
+      spos = (long(sidx) * NSTEP + j + sl) * SWD + sl;
     }
+    auto IX = [&](int F, int f) -> long { return SWD > 0 ? (spos - sl) * F + long(f) * SWD + sl : long(f) * g.N + p; };
+    using Rc = Rec<NS, NT>;
     if (mode == 0) {
       // coupled: dS_z/dz, z = (rho, m_x, m_y, rhoE, [rhoe_ve], rho_0..rho_{ns-2})
       // storage derivative of omega_s: dw/dq_j = dw_dr + dw_dT dT/dq_j + dw_dTv dTv/dq_j
@@ -499,23 +550,22 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
       for (int r = 0; r < NB; ++r)
 #pragma unroll
-        for (int c = 0; c < NB; ++c) Di[long(r * NB + c) * STR + pos] = RT(Ai[r][c]);
+        for (int c = 0; c < NB; ++c) Di[IX(Rc::NDINV, r * NB + c)] = RT(Ai[r][c]);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
-      bb[0 * STR + pos] = RT(-rsum);
-      bb[1 * STR + pos] = RT(-R[NS]);
-      bb[2 * STR + pos] = RT(-R[NS + 1]);
-      bb[3 * STR + pos] = RT(-R[NS + 2]);
-      if (NT == 2) bb[4 * STR + pos] = RT(-R[NS + 3]);
+      bb[IX(Rc::NSOL, 0)] = RT(-rsum);
+      bb[IX(Rc::NSOL, 1)] = RT(-R[NS]);
+      bb[IX(Rc::NSOL, 2)] = RT(-R[NS + 1]);
+      bb[IX(Rc::NSOL, 3)] = RT(-R[NS + 2]);
+      if (NT == 2) bb[IX(Rc::NSOL, 4)] = RT(-R[NS + 3]);
 #pragma unroll
-      for (int s = 0; s < NS - 1; ++s) bb[long(NF + s) * STR + pos] = RT(-R[s]);
+      for (int s = 0; s < NS - 1; ++s) bb[IX(Rc::NSOL, NF + s)] = RT(-R[s]);
     } else {
       double dF = Vdt + 0.5 * slam + svF;
       double dC = Vdt + 0.5 * sU + svC;
       RT *DF = reinterpret_cast<RT *>(out.Dinv);
-      RT *DC = DF + 6 * STR;
-      // flow block: scalar rows, plus the rho e_ve row -V d omega_ve/dQ_F (frozen Y)
+            // flow block: scalar rows, plus the rho e_ve row -V d omega_ve/dQ_F (frozen Y)
       double df6[6];
       df6[0] = 1.0 / dF;
       for (int k = 1; k < 6; ++k) df6[k] = 0.0;
@@ -529,71 +579,97 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         df6[5] = 1.0 / piv;
       }
 #pragma unroll
-      for (int k = 0; k < 6; ++k) DF[long(k) * STR + pos] = RT(df6[k]);
+      for (int k = 0; k < 6; ++k) DF[IX(Rc::NDINV, k)] = RT(df6[k]);
       double A[NS][NS], Ai[NS][NS];
+      bool use_sur = false, ok = false;
+      if (try_sur) {
+        // surrogate J_C, accepted when D_C = dC I - V J_C is strictly row
+        // diagonally dominant with a positive diagonal in molar units
+        // (rows and columns scaled to concentrations rho_s / M_s):
+        //   D_rr M_r > sum_{c != r} |D_rc| M_c
+        bool dd = true;
 #pragma unroll
-      for (int r = 0; r < NS; ++r)
+        for (int r = 0; r < NS; ++r) {
+          double off = 0.0;
 #pragma unroll
-        for (int c = 0; c < NS; ++c) A[r][c] = (r == c ? dC : 0.0) - Vp * C.dw_dr[r][c];
-      bool ok = invert<NS>(A, Ai);
+          for (int c = 0; c < NS; ++c) {
+            A[r][c] = (r == c ? dC : 0.0) - Vp * double(out.Jsur[size_t(r * NS + c) * g.N + p]);
+            if (c != r) off += fabs(A[r][c]) * m.M[c];
+          }
+          dd = dd && A[r][r] > 0.0 && A[r][r] * m.M[r] > off;
+        }
+        if (dd) ok = invert<NS>(A, Ai);
+        use_sur = dd && ok;
+        if (!use_sur) {
+          atomicAdd(out.ddfail, 1ull);
+          if (!have_jac) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
+        }
+      }
+      if (!use_sur) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r)
+#pragma unroll
+          for (int c = 0; c < NS; ++c) A[r][c] = (r == c ? dC : 0.0) - Vp * C.dw_dr[r][c];
+        ok = invert<NS>(A, Ai);
+      }
       if (!ok && out.bad) atomicMin(out.bad, p);
 #pragma unroll
       for (int r = 0; r < NS; ++r)
 #pragma unroll
-        for (int c = 0; c < NS; ++c) DC[long(r * NS + c) * STR + pos] = RT(Ai[r][c]);
+        for (int c = 0; c < NS; ++c) DF[IX(Rc::NDINV, 6 + r * NS + c)] = RT(Ai[r][c]);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
-      bb[0 * STR + pos] = RT(-rsum);
-      bb[1 * STR + pos] = RT(-R[NS]);
-      bb[2 * STR + pos] = RT(-R[NS + 1]);
-      bb[3 * STR + pos] = RT(-R[NS + 2]);
-      if (NT == 2) bb[4 * STR + pos] = RT(-R[NS + 3]);
+      bb[IX(Rc::NSOL, 0)] = RT(-rsum);
+      bb[IX(Rc::NSOL, 1)] = RT(-R[NS]);
+      bb[IX(Rc::NSOL, 2)] = RT(-R[NS + 1]);
+      bb[IX(Rc::NSOL, 3)] = RT(-R[NS + 2]);
+      if (NT == 2) bb[IX(Rc::NSOL, 4)] = RT(-R[NS + 3]);
 #pragma unroll
-      for (int s = 0; s < NS; ++s) bb[long(NF + s) * STR + pos] = RT(-R[s]);
+      for (int s = 0; s < NS; ++s) bb[IX(Rc::NSOL, NF + s)] = RT(-R[s]);
     }
     if (out.strip_w > 0) {
       // JVP state of this cell and the coefficients of its four pushes
       RT *st = reinterpret_cast<RT *>(out.state);
       RT *fc = reinterpret_cast<RT *>(out.face);
-      st[0 * STR + pos] = RT(P.u);
-      st[1 * STR + pos] = RT(P.v);
-      st[2 * STR + pos] = RT(P.H);
-      st[3 * STR + pos] = RT(P.eve);
-      st[4 * STR + pos] = RT(P.pE);
-      st[5 * STR + pos] = RT(P.pv);
+      st[IX(Rc::NSTATE, 0)] = RT(P.u);
+      st[IX(Rc::NSTATE, 1)] = RT(P.v);
+      st[IX(Rc::NSTATE, 2)] = RT(P.H);
+      st[IX(Rc::NSTATE, 3)] = RT(P.eve);
+      st[IX(Rc::NSTATE, 4)] = RT(P.pE);
+      st[IX(Rc::NSTATE, 5)] = RT(P.pv);
       if (mode == 0) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          st[long(6 + s) * STR + pos] = RT(P.Y[s]);
-          st[long(6 + NS + s) * STR + pos] = RT(P.pr[s]);
+          st[IX(Rc::NSTATE, 6 + s)] = RT(P.Y[s]);
+          st[IX(Rc::NSTATE, 6 + NS + s)] = RT(P.pr[s]);
         }
       } else {
         double prY = 0.0;
 #pragma unroll
         for (int s = 0; s < NS; ++s) prY += P.pr[s] * P.Y[s];
-        st[6 * STR + pos] = RT(prY);
+        st[IX(Rc::NSTATE, 6)] = RT(prY);
       }
       const int rv = mode == 0 ? R_LVK : R_LVF;
       // E face = i-face (i+1, j), N face = j-face (i, j+1): outward normals of the
       // receiving neighbours are -n; W face = i-face (i, j), S face = j-face (i, j): +n
       const double SEh = 0.5 * SE, SNh = 0.5 * SN, SWh = 0.5 * SW, SSh = 0.5 * SS;
-      fc[0 * STR + pos] = RT(-SEh * g.fi_nx[fE]);
-      fc[1 * STR + pos] = RT(-SEh * g.fi_ny[fE]);
-      fc[2 * STR + pos] = RT(-SNh * g.fj_nx[fN]);
-      fc[3 * STR + pos] = RT(-SNh * g.fj_ny[fN]);
-      fc[4 * STR + pos] = RT(SWh * g.fi_nx[fW]);
-      fc[5 * STR + pos] = RT(SWh * g.fi_ny[fW]);
-      fc[6 * STR + pos] = RT(SSh * g.fj_nx[fS]);
-      fc[7 * STR + pos] = RT(SSh * g.fj_ny[fS]);
-      fc[8 * STR + pos] = RT(SEh * Ri[size_t(R_LAM) * nfi + fE] + SE * Ri[size_t(rv) * nfi + fE]);
-      fc[9 * STR + pos] = RT(SNh * Rj[size_t(R_LAM) * nfj + fN] + SN * Rj[size_t(rv) * nfj + fN]);
-      fc[10 * STR + pos] = RT(SWh * Ri[size_t(R_LAM) * nfi + fW] + SW * Ri[size_t(rv) * nfi + fW]);
-      fc[11 * STR + pos] = RT(SSh * Rj[size_t(R_LAM) * nfj + fS] + SS * Rj[size_t(rv) * nfj + fS]);
-      fc[12 * STR + pos] = RT(SEh * Ri[size_t(R_UABS) * nfi + fE] + SE * Ri[size_t(R_LVC) * nfi + fE]);
-      fc[13 * STR + pos] = RT(SNh * Rj[size_t(R_UABS) * nfj + fN] + SN * Rj[size_t(R_LVC) * nfj + fN]);
-      fc[14 * STR + pos] = RT(SWh * Ri[size_t(R_UABS) * nfi + fW] + SW * Ri[size_t(R_LVC) * nfi + fW]);
-      fc[15 * STR + pos] = RT(SSh * Rj[size_t(R_UABS) * nfj + fS] + SS * Rj[size_t(R_LVC) * nfj + fS]);
+      fc[IX(Rc::NFACE, 0)] = RT(-SEh * g.fi_nx[fE]);
+      fc[IX(Rc::NFACE, 1)] = RT(-SEh * g.fi_ny[fE]);
+      fc[IX(Rc::NFACE, 2)] = RT(-SNh * g.fj_nx[fN]);
+      fc[IX(Rc::NFACE, 3)] = RT(-SNh * g.fj_ny[fN]);
+      fc[IX(Rc::NFACE, 4)] = RT(SWh * g.fi_nx[fW]);
+      fc[IX(Rc::NFACE, 5)] = RT(SWh * g.fi_ny[fW]);
+      fc[IX(Rc::NFACE, 6)] = RT(SSh * g.fj_nx[fS]);
+      fc[IX(Rc::NFACE, 7)] = RT(SSh * g.fj_ny[fS]);
+      fc[IX(Rc::NFACE, 8)] = RT(SEh * Ri[size_t(R_LAM) * nfi + fE] + SE * Ri[size_t(rv) * nfi + fE]);
+      fc[IX(Rc::NFACE, 9)] = RT(SNh * Rj[size_t(R_LAM) * nfj + fN] + SN * Rj[size_t(rv) * nfj + fN]);
+      fc[IX(Rc::NFACE, 10)] = RT(SWh * Ri[size_t(R_LAM) * nfi + fW] + SW * Ri[size_t(rv) * nfi + fW]);
+      fc[IX(Rc::NFACE, 11)] = RT(SSh * Rj[size_t(R_LAM) * nfj + fS] + SS * Rj[size_t(rv) * nfj + fS]);
+      fc[IX(Rc::NFACE, 12)] = RT(SEh * Ri[size_t(R_UABS) * nfi + fE] + SE * Ri[size_t(R_LVC) * nfi + fE]);
+      fc[IX(Rc::NFACE, 13)] = RT(SNh * Rj[size_t(R_UABS) * nfj + fN] + SN * Rj[size_t(R_LVC) * nfj + fN]);
+      fc[IX(Rc::NFACE, 14)] = RT(SWh * Ri[size_t(R_UABS) * nfi + fW] + SW * Ri[size_t(R_LVC) * nfi + fW]);
+      fc[IX(Rc::NFACE, 15)] = RT(SSh * Rj[size_t(R_UABS) * nfj + fS] + SS * Rj[size_t(R_LVC) * nfj + fS]);
     }
     }
   }
@@ -616,12 +692,23 @@ reduce:
   }
 }
 
+// Stall policy of the surrogate (surr_off non-null): once `window` iterations
+// have run with it since iteration it_on, the first iteration whose density
+// residual exceeds `ratio` times the one `window` iterations earlier switches
+// it off for the rest of the run (*surr_off = that iteration).
+struct StallArgs {
+  int *surr_off;
+  int it_on, window;
+  double ratio;
+};
+
 // Final fixed-order reduction of the norm partials (one block); records the
 // history and sets the stop flag once r/r0 <= tol.
 template <int NS>
 __global__ void __launch_bounds__(256) k_norms(const double *__restrict__ part, int nblk, double *__restrict__ norms,
                                                double *__restrict__ hist, int it, int hist_max, double *__restrict__ r0,
-                                               double tol, int *__restrict__ done, int *__restrict__ it_done) {
+                                               double tol, int *__restrict__ done, int *__restrict__ it_done,
+                                               StallArgs stall) {
   if (done && *done) return;
   __shared__ double red[2][256];
   double a = 0.0, b = 0.0;
@@ -645,6 +732,9 @@ __global__ void __launch_bounds__(256) k_norms(const double *__restrict__ part, 
       if (it == 0 || *r0 == 0.0) *r0 = nr;
       if (done && tol > 0.0 && nr <= tol * (*r0)) { *done = 1; if (it_done) *it_done = it; }
     }
+    if (stall.surr_off && *stall.surr_off < 0 && hist && it - stall.it_on >= stall.window && it < hist_max &&
+        it - stall.window >= 0 && nr > stall.ratio * hist[2 * (it - stall.window)])
+      *stall.surr_off = it;
   }
 }
 

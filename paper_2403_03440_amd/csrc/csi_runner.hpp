@@ -3,6 +3,7 @@
 // csi_inst.hip and dispatched through the IRunner interface.
 #pragma once
 #include "csi_strip.hpp"
+#include "csi_surrogate.hpp"
 
 namespace csi {
 
@@ -19,8 +20,14 @@ struct WS {
   int strip_w;               // 0: one launch per hyperplane; 16 or 64: persistent strip kernels
   int pub_every;             // strip progress published every this many steps
   long spin_limit;
+  SurArgs sur;               // surrogate network (packed operands, biases, scales) and its J_C buffer
 };
-enum { FL_BAD = 0, FL_DONE = 1, FL_ITDONE = 2, FL_CLIP = 3, FL_SING = 4, FL_ABORT = 5, FL_N = 8 };
+// flags[]: ints, with one 64-bit counter at int offset FL_DDFAIL
+enum {
+  FL_BAD = 0, FL_DONE = 1, FL_ITDONE = 2, FL_CLIP = 3, FL_SING = 4, FL_ABORT = 5, FL_SURR_OFF = 6, FL_DDFAIL = 8,
+  FL_N = 16
+};
+inline unsigned long long *ddfail_counter(int *flags) { return reinterpret_cast<unsigned long long *>(flags + FL_DDFAIL); }
 
 class IRunner {
  public:
@@ -30,8 +37,12 @@ class IRunner {
   virtual hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
   virtual hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                           bool stoppable) = 0;
-  virtual hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable) = 0;
-  virtual hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable) = 0;
+  virtual hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable,
+                           StallArgs stall = StallArgs{nullptr, 0, 0, 0.0}) = 0;
+  virtual hipError_t surrogate(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
+  virtual hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc) = 0;
+  virtual hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable,
+                            hipEvent_t mid = nullptr) = 0;
   virtual hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind,
                             bool stoppable) = 0;
   virtual hipError_t q_from_prim_host(const Mech &m, const double *rs, double u, double v, double T, double Tv,
@@ -63,7 +74,8 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                   bool stoppable) override {
-    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, w.state, w.face, w.src, w.flags + FL_SING, w.strip_w};
+    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, w.state, w.face, w.src, w.flags + FL_SING, w.strip_w,
+              w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
       hipLaunchKernelGGL((k_cell<NS, NT, double>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
@@ -74,39 +86,50 @@ template <int NS, int NT> class Runner : public IRunner {
     return hipGetLastError();
   }
 
-  hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable) override {
+  hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable, StallArgs stall) override {
     hipLaunchKernelGGL(k_norms<NS>, dim3(1), dim3(256), 0, st, w.part, w.nblk_cell, w.norms, stoppable ? w.hist : nullptr,
                        it, w.hist_max, stoppable ? w.r0 : nullptr, tol, stoppable ? w.flags + FL_DONE : nullptr,
-                       w.flags + FL_ITDONE);
+                       w.flags + FL_ITDONE, stall);
     return hipGetLastError();
   }
 
-  template <typename RT> hipError_t sweeps_t(const Geo &g, const WS &w, hipStream_t st, int mode, bool stoppable) {
+  hipError_t surrogate(const Geo &g, const WS &w, hipStream_t st, bool stoppable) override {
+    hipLaunchKernelGGL((k_surrogate<NS, NT>), dim3(nblocks(g.N, 64)), dim3(256), 0, st, g, w.prim, w.sur,
+                       w.flags + FL_SURR_OFF, stoppable ? w.flags + FL_DONE : nullptr);
+    return hipGetLastError();
+  }
+
+  hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc) override {
+    hipError_t e = prim(g, w, st, false);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sample<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, xr, jc);
+    return hipGetLastError();
+  }
+
+  // mid (optional) is recorded between the forward and the backward sweep
+  template <typename RT>
+  hipError_t sweeps_t(const Geo &g, const WS &w, hipStream_t st, int mode, bool stoppable, hipEvent_t mid) {
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (w.strip_w > 0) {
       StripMap sm = strip_map(g.ni, g.nj, w.strip_w);
-      int *prog = w.sync, *progb = w.sync + sm.nstrip, *ticket = w.sync + 2 * sm.nstrip;
-      StripArgs a{w.b, w.Dinv, w.state, w.face, w.dqs, w.dq, w.bnd, prog, progb, ticket, w.flags + FL_ABORT, mode,
-                  w.pub_every, w.spin_limit};
-      hipLaunchKernelGGL(k_zero_ints<NS>, dim3(1), dim3(64), 0, st, w.sync, 2 * sm.nstrip + 2, done);
-      const dim3 gr(sm.nstrip), bl(64);
+      StripArgs a{w.b, w.Dinv, w.state, w.face, w.dqs, w.dq, w.bnd, w.sync, w.flags + FL_ABORT, w.pub_every,
+                  w.spin_limit};
+      hipLaunchKernelGGL(k_zero_ints<NS>, dim3(1), dim3(64), 0, st, w.sync, strip_sync_ints(sm.nstrip), done);
+      // split: one wavefront per strip for each of the two independent parts
+      const dim3 gr(sm.nstrip, mode == 0 ? 1 : 2), bl(64);
       if (w.strip_w == 16 || NS > 11) {  // 64-column strips are compiled for ns <= 11 only
-        if (mode == 0) {
-          hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
-          hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
-        } else {
-          hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
-          hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
-        }
+        if (mode == 0) hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
+        else hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
+        if (mid) (void)hipEventRecord(mid, st);
+        if (mode == 0) hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
+        else hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
       } else {
         if constexpr (NS <= 11) {
-          if (mode == 0) {
-            hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
-            hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
-          } else {
-            hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
-            hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
-          }
+          if (mode == 0) hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
+          else hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
+          if (mid) (void)hipEventRecord(mid, st);
+          if (mode == 0) hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
+          else hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
         }
       }
       return hipGetLastError();
@@ -118,6 +141,7 @@ template <int NS, int NT> class Runner : public IRunner {
       int len = j1 - j0 + 1;
       hipLaunchKernelGGL((k_sweep_fwd_hp<NS, NT, RT>), dim3(nblocks(len, 64)), dim3(64), 0, st, g, a, k, done);
     }
+    if (mid) (void)hipEventRecord(mid, st);
     for (int k = K - 1; k >= 0; --k) {
       int j0 = k - g.ni + 1 > 0 ? k - g.ni + 1 : 0, j1 = k < g.nj - 1 ? k : g.nj - 1;
       int len = j1 - j0 + 1;
@@ -126,8 +150,9 @@ template <int NS, int NT> class Runner : public IRunner {
     return hipGetLastError();
   }
 
-  hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable) override {
-    return prec == 0 ? sweeps_t<double>(g, w, st, mode, stoppable) : sweeps_t<float>(g, w, st, mode, stoppable);
+  hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable,
+                    hipEvent_t mid) override {
+    return prec == 0 ? sweeps_t<double>(g, w, st, mode, stoppable, mid) : sweeps_t<float>(g, w, st, mode, stoppable, mid);
   }
 
   hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind, bool stoppable) override {

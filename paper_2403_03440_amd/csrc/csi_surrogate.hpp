@@ -1,0 +1,86 @@
+// Solver-side kernels of the species-Jacobian surrogate: training samples
+// (features and the exact J_C = d omega_s / d rho_r at fixed T, Tv, the block
+// the split species diagonal carries, Section 2.3) and network inference per
+// cell into an FP32 buffer that the cell kernel assembles D_C from.
+#pragma once
+#include "csi_kernels.hpp"
+#include "csi_mlp_core.hpp"
+
+namespace csi {
+
+struct SurArgs {
+  const u16x8 *P;         // packed BF16 operands
+  const float *p;         // FP32 master vector (biases)
+  const double *scales;   // mu[n_in], sigma[n_in], tau0
+  float *J;               // [ns * ns][N], entry (s, r) at row s * ns + r
+};
+
+// Cell features (ln T, ln Tv, ln rho, Y_1..Y_ns) of padded cell pc.
+template <int NS, int NT>
+__device__ inline double sur_feature(const double *__restrict__ prim, size_t NP, long pc, int k) {
+  if (k == 0) return log(prim[F_T * NP + pc]);
+  if (k == 1) return log(prim[(NT == 2 ? F_TV : F_T) * NP + pc]);
+  if (k == 2) return log(prim[F_RHO * NP + pc]);
+  return prim[size_t(PF<NS>::Y + k - 3) * NP + pc];
+}
+
+template <int NS, int NT>
+__global__ void __launch_bounds__(256) k_sample(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
+                                                const double *__restrict__ prim, int n, float *__restrict__ xr,
+                                                float *__restrict__ jc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Mech &m = *mech;
+  const size_t NP = g.NP;
+  const int i = p % g.ni, j = p / g.ni;
+  const long pc = padc(g, i, j);
+  constexpr int NIN = NS + 3;
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) xr[long(p) * NIN + k] = float(sur_feature<NS, NT>(prim, NP, pc, k));
+  double rs[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rs[s] = Q[size_t(s) * g.N + p];
+  Chem<NS, NT> C;
+  chemistry<NS, NT, true>(m, rs, prim[F_T * NP + pc], prim[F_TV * NP + pc], prim[F_P * NP + pc], C);
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int r = 0; r < NS; ++r) jc[long(p) * NS * NS + s * NS + r] = float(C.dw_dr[s][r]);
+}
+
+// One block = 64 cells (4 waves x 16); J = sinh(y) / tau0.
+template <int NS, int NT>
+__global__ void __launch_bounds__(256) k_surrogate(Geo g, const double *__restrict__ prim, SurArgs a,
+                                                   const int *__restrict__ off, const int *__restrict__ done) {
+  if ((done && *done) || *off >= 0) return;
+  constexpr int NIN = NS + 3, KS1 = (NIN + 31) / 32;
+  const MlpDims d = mlp_dims(NIN, NS * NS);
+  const int lane = threadIdx.x & 63, gq = lane >> 4, jl = lane & 15;
+  const int p = blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + jl;
+  const bool valid = p < g.N;
+  const long pc = valid ? padc(g, p % g.ni, p / g.ni) : 0;
+  u16x8 xin[KS1];
+#pragma unroll
+  for (int s = 0; s < KS1; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = mlp_kmap(s, gq, e);
+      float v = 0.f;
+      if (valid && k < NIN) v = float((sur_feature<NS, NT>(prim, g.NP, pc, k) - a.scales[k]) / a.scales[NIN + k]);
+      xin[s][e] = f2bf(v);
+    }
+  float h1[4][4], h2[4][4];
+  u16x8 B2[2];
+  mlp_hidden<KS1>(d, a.P, a.p, xin, h1, h2, B2);
+  const double itau = 1.0 / a.scales[2 * NIN];
+  for (int t = 0; t < d.nt3; ++t) {
+    f32x4 y = mlp_out_tile(d, a.P, a.p, B2, t);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 16 * t + 4 * gq + r;
+      if (valid && o < NS * NS) a.J[size_t(o) * g.N + p] = float(sinh(double(y[r])) * itau);
+    }
+  }
+}
+
+}  // namespace csi

@@ -232,16 +232,21 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.N) return;
   const RT *dq = reinterpret_cast<const RT *>(dqv);
-  long STR = g.N, pos = p;
+  // component k of the increment: cell-major, or step-blocked strip layout
+  long spos = 0;
+  int sl = 0;
   if (strip_w > 0) {
-    int W = strip_w, i = p % g.ni, j = p / g.ni, sidx = i / W, l = i - sidx * W, NSTEP = g.nj + W - 1;
-    STR = long((g.ni + W - 1) / W) * NSTEP * W;
-    pos = (long(sidx) * NSTEP + j + l) * W + l;
+    const int i = p % g.ni, j = p / g.ni, sidx = i / strip_w, NSTEP = g.nj + strip_w - 1;
+    sl = i - sidx * strip_w;
+    spos = (long(sidx) * NSTEP + j + sl) * strip_w + sl;
   }
+  auto IX = [&](int k) -> long {
+    return strip_w > 0 ? (spos - sl) * Rec<NS, NT>::NSOL + long(k) * strip_w + sl : long(k) * g.N + p;
+  };
   double rs[NS], rho = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) { rs[s] = Q[size_t(s) * g.N + p]; rho += rs[s]; }
-  double drho = double(dq[pos]);
+  double drho = double(dq[IX(0)]);
   double target = rho + drho;
   double nr[NS];
   bool clip = false;
@@ -249,7 +254,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
     double sum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s) {
-      double d = double(dq[long(NF + s) * STR + pos]);
+      double d = double(dq[IX(NF + s)]);
       nr[s] = rs[s] + d;
       sum += d;
     }
@@ -257,14 +262,14 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   } else if (kind == 1) {
     double sum = 0.0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sum += double(dq[long(NF + s) * STR + pos]);
+    for (int s = 0; s < NS; ++s) sum += double(dq[IX(NF + s)]);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) nr[s] = rs[s] + double(dq[long(NF + s) * STR + pos]) + (rs[s] / rho) * (drho - sum);
+    for (int s = 0; s < NS; ++s) nr[s] = rs[s] + double(dq[IX(NF + s)]) + (rs[s] / rho) * (drho - sum);
   } else {
     double t[NS], sum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      double v = rs[s] + double(dq[long(NF + s) * STR + pos]);
+      double v = rs[s] + double(dq[IX(NF + s)]);
       if (v < 0.0) clip = true;
       t[s] = v > 0.0 ? v : 0.0;
       sum += t[s];
@@ -288,12 +293,12 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   if (!(target > 0.0) && bad) atomicMin(bad, p);
 #pragma unroll
   for (int s = 0; s < NS; ++s) Q[size_t(s) * g.N + p] = nr[s];
-  Q[size_t(NS) * g.N + p] += double(dq[1 * STR + pos]);
-  Q[size_t(NS + 1) * g.N + p] += double(dq[2 * STR + pos]);
-  Q[size_t(NS + 2) * g.N + p] += double(dq[3 * STR + pos]);
+  Q[size_t(NS) * g.N + p] += double(dq[IX(1)]);
+  Q[size_t(NS + 1) * g.N + p] += double(dq[IX(2)]);
+  Q[size_t(NS + 2) * g.N + p] += double(dq[IX(3)]);
   if (NT == 2) {
     // positivity of the vibrational-electronic energy: floor at Tv = TV_FLOOR
-    double eve = Q[size_t(NS + 3) * g.N + p] + double(dq[4 * STR + pos]), fl = 0.0;
+    double eve = Q[size_t(NS + 3) * g.N + p] + double(dq[IX(4)]), fl = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) fl += nr[s] * eve_s(*mech, s, TV_FLOOR);
     if (eve < fl) {

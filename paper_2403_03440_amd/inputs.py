@@ -472,3 +472,9 @@ def random_prims(mech: Mechanism, n: int, seed: int, T_range=(300.0, 9000.0), rh
     ang = rng.uniform(0, 2 * np.pi, n)
     sp = speed * rng.uniform(0, 1, n)
     return (np.ascontiguousarray(rho[None, :] * Y), sp * np.cos(ang), sp * np.sin(ang), T, Tv)
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """Seeded permutation of 0..n-1: indices ordered by splitmix64(seed XOR i)."""
+    keys = splitmix64(np.uint64(seed) ^ np.arange(n, dtype=np.uint64))
+    return np.argsort(keys, kind="stable").astype(np.int32)
