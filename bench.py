@@ -36,7 +36,7 @@ VARIANTS = {  # name: (mode, correction kind, precision, species Jacobian 0 exac
     "split64": (1, 2, 0, 0), "coupled64": (0, 0, 0, 0), "splitmixed": (1, 2, 1, 0), "coupledmixed": (0, 0, 1, 0),
     "splitmixed_mlp": (1, 2, 1, 1)}
 HEADLINE = "splitmixed_mlp"
-SWEEP_SOURCES = ["csi_strip.hpp", "csi_sweep.hpp", "csi_phys.hpp"]
+SWEEP_SOURCES = ["csi_group.hpp", "csi_kernels.hpp", "csi_sweep.hpp", "csi_phys.hpp"]
 
 
 def nsol(m, mode):

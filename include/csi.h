@@ -134,13 +134,18 @@ int csi_norm_history(csi_ctx *ctx, int n, double *hist);
  * arrays): rho_s [ns][n], u, v, T, Tv [n] -> q [nv][n] */
 int csi_prim_to_cons(csi_ctx *ctx, int n, const double *rho_s, const double *u, const double *v, const double *T,
                      const double *Tv, double *q);
-/* Sweep schedule: width 0 launches one kernel per i+j hyperplane; width 16 or 64
- * runs each sweep as one persistent kernel with one wavefront per strip of that
- * many columns (default 64 for ns <= 11, else 16), whose progress is published to the neighbouring
- * strip every publish_every steps (1..64, default 4). */
-int csi_set_sweep(csi_ctx *ctx, int width, int publish_every);
+/* Sweep schedule (Section 2.2 sweeps in i+j order).  schedule 0 launches one
+ * kernel per i+j hyperplane with cell-major records.  schedule 1 (default)
+ * runs each sweep as one persistent kernel: every cell of a strip is owned by
+ * a group of G lanes of one wavefront (G = unknowns of the swept part: nb
+ * coupled, nf flow, ns species) and a wavefront holds C = 64 / G columns.
+ * Errors: CSI_ERR_ARG for any other value.  Changing the schedule invalidates
+ * the records of the last implicit operator (csi_get_array). */
+int csi_set_sweep(csi_ctx *ctx, int schedule);
 /* Phase timing of csi_step with HIP events on the context's stream (on = 1 to
- * enable).  csi_phase_times returns the accumulated milliseconds of the
+ * enable; on = 2 also records a per-strip trace of the group-schedule sweeps,
+ * read with csi_get_array(ctx, "sweep_trace"); 0 disables both).
+ * csi_phase_times returns the accumulated milliseconds of the
  * phases [prim, faces, cell, norms, sweep_fwd, sweep_bwd, update] (ms[0..6])
  * and the number of timed iterations in ms[7]; reset = 1 clears the
  * accumulators.  ms must hold 8 doubles. */
@@ -149,8 +154,14 @@ int csi_phase_times(csi_ctx *ctx, double *ms, int reset);
 
 /* Debug / parity access to named workspace arrays, copied to host as FP64:
  * "R" [nv][N], "dtau" [N], "src" [nv][N], "b" "dqs" "dq" [nsol][N], "T" "Tv" "p" "c" [N],
- * "qw" [ni], "Dinv" (coupled [nb*nb][N]; split [6 + ns*ns][N]), "Jsur" [ns*ns][N]
- * (surrogate species block of the last surrogate iteration). */
+ * "qw" [ni], "Dinv" (coupled [nb*nb][N] row-major D^-1; split [nf*nf + ns*ns][N]: the
+ * flow block's inverse as a dense matrix, then the species inverse), "Jsur" [ns*ns][N]
+ * (surrogate species block of the last surrogate iteration), "sweep_trace"
+ * [2 sweeps (fwd, bwd)][2 parts][ni strips][8] of the last sweep pair with the
+ * trace on: wall clock (100 MHz ticks) at the compute wave's start and end,
+ * its spins on step records and on boundary pushes, the copy wave's spins on
+ * free ring slots and the boundary wave's spins on pushes (unused entries are
+ * stale). */
 int csi_get_array(csi_ctx *ctx, const char *name, double *out, size_t count);
 
 /* ------------------------------------------------------------------------

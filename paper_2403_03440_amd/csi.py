@@ -221,11 +221,12 @@ class Solver:
         N = self.N
         mode = self.last_mode if mode is None else mode
         shapes = {"R": (m.nv, N), "dtau": (N,), "src": (m.nv, N), "qw": (self.ni,), "T": (N,), "Tv": (N,),
-                  "p": (N,), "c": (N,), "Jsur": (m.ns * m.ns, N)}
+                  "p": (N,), "c": (N,), "Jsur": (m.ns * m.ns, N),
+                  "sweep_trace": (2, 2, self.ni, 8)}
         if name in ("b", "dqs", "dq"):
             shape = (self.nsol(mode), N)
         elif name == "Dinv":
-            shape = (m.nb * m.nb, N) if mode == COUPLED else (6 + m.ns * m.ns, N)
+            shape = (m.nb * m.nb, N) if mode == COUPLED else (m.nf * m.nf + m.ns * m.ns, N)
         else:
             shape = shapes[name]
         out = np.zeros(shape)
@@ -241,11 +242,12 @@ class Solver:
         self._check(self.L.csi_prim_to_cons(self.ctx, n, *[p for _, p in args], q.ctypes.data_as(_dp)))
         return q
 
-    def set_sweep(self, width, publish_every=4):
-        """0: one launch per hyperplane; 16 or 64: persistent strip-wavefront kernels"""
-        self._check(self.L.csi_set_sweep(self.ctx, int(width), int(publish_every)))
+    def set_sweep(self, schedule):
+        """0: one launch per i+j hyperplane; 1: persistent group kernels (default)"""
+        self._check(self.L.csi_set_sweep(self.ctx, int(schedule)))
 
     def set_timing(self, on=True):
+        """1: phase timing with HIP events; 2: also a per-strip sweep trace (get("sweep_trace"))"""
         self._check(self.L.csi_set_timing(self.ctx, int(on)))
 
     def phase_times(self, reset=False):

@@ -65,10 +65,11 @@ struct csi_ctx {
   WS w;
   Geo g;
   long it_global = 0;
-  int strip_w = 16;  // sweep schedule: 0 hyperplane launches, 16 / 64 persistent strips
-  int pub_every = 4;  // strip progress publication interval (steps)
+  int group_c = 1;  // sweep schedule: 0 hyperplane launches; 1 persistent group kernels
   // phase timing (HIP events, created on first use)
   bool timing = false;
+  int trace = 0;                     // per-strip sweep trace (csi_set_timing(ctx, 2))
+  long long *trace_buf = nullptr;
   std::vector<hipEvent_t> ev;
   double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
@@ -89,11 +90,31 @@ int hip_check(csi_ctx *c, hipError_t e, const char *what) {
 }
 
 struct Layout {
-  size_t off[48];
+  size_t off[64];
   size_t total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+// bytes of the group-schedule arrays of one part (C = 64 / G cells per
+// wave): the larger of the two element sizes (the precision can change after
+// binding)
+struct GroupCap {
+  size_t R = 0, x = 0, bnd = 0;
+  void merge(const GroupCap &o) { R = std::max(R, o.R); x = std::max(x, o.x); bnd = std::max(bnd, o.bnd); }
+};
+GroupCap group_cap(int ni, int nj, PartShape p) {
+  GroupCap r;
+  for (int esz = 4; esz <= 8; esz += 4) {
+    const GroupMap m = group_map(ni, nj, p, 64 / p.G, esz);
+    GroupCap t;
+    t.R = size_t(m.nblk) * m.RW * esz;
+    t.x = size_t(m.nblk) * m.Lw * esz;
+    t.bnd = size_t(m.nstrip) * nj * p.G * esz;
+    r.merge(t);
+  }
+  return r;
+}
 
 // workspace layout (bytes); order fixed, every block 256-byte aligned
 Layout layout(const csi_ctx *c, int nprim) {
@@ -105,10 +126,11 @@ Layout layout(const csi_ctx *c, int nprim) {
   const int nv = c->nv(), nsol = c->nsplit();
   const size_t ndinv = std::max<size_t>(size_t(c->nb()) * c->nb(), 6 + size_t(c->ns) * c->ns);
   const size_t nblk = (N + 255) / 256;
-  // per-cell sweep records: cell-major (N) or strip layout (up to the widest strip)
-  const StripMap sm = strip_map(c->ni, c->nj, 16), sm64 = strip_map(c->ni, c->nj, 64);
-  const size_t A = std::max<size_t>(N, std::max<size_t>(sm.LEN, sm64.LEN));
-  const size_t nstrip = std::max(sm.nstrip, sm64.nstrip);
+  const size_t A = N;
+  // group-schedule records, per part
+  GroupCap g0 = group_cap(c->ni, c->nj, part_shape(PART_COUPLED, c->ns, c->nt));
+  g0.merge(group_cap(c->ni, c->nj, part_shape(PART_FLOW, c->ns, c->nt)));
+  const GroupCap g1 = group_cap(c->ni, c->nj, part_shape(PART_SPECIES, c->ns, c->nt));
   const MlpDims sd = mlp_dims(c->ns + 3, c->ns * c->ns);
   size_t sizes[] = {
       sizeof(Mech),                       // 0 mech
@@ -123,17 +145,16 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(nv) * N * 8, N * 8, size_t(nv) * N * 8,   // 19-21 R dtau src
       size_t(c->ni) * 8, 2 * nblk * 8, 2 * 8, 8,       // 22-25 qw part norms r0
       size_t(2) * HIST_MAX * 8,                       // 26 hist
-      size_t(nsol) * A * 8, size_t(nsol) * A * 8, size_t(nsol) * A * 8,  // 27-29 b dqs dq
-      ndinv * A * 8,                                  // 30 Dinv
+      size_t(nsol) * A * 8, size_t(nsol) * A * 8, size_t(nsol) * A * 8,  // 27-29 b dqs dq (hyperplane schedule)
+      ndinv * A * 8,                                  // 30 Dinv (hyperplane schedule)
       FL_N * 4,                                       // 31 flags
-      size_t(6 + 2 * c->ns) * A * 8,                  // 32 strip state records
-      size_t(16) * A * 8,                             // 33 strip face records
-      size_t(nstrip) * c->nj * nsol * 8,              // 34 strip-boundary pushes
-      size_t(strip_sync_ints(int(nstrip))) * 4,       // 35 strip progress counters and tickets (two parts)
-      size_t(c->ns) * c->ns * N * 4,                  // 36 surrogate J_C
-      size_t(sd.nslots) * 16,                         // 37 surrogate packed operands
-      size_t(sd.np) * 4,                              // 38 surrogate FP32 parameters
-      size_t(2 * sd.n_in + 1) * 8,                    // 39 surrogate scales
+      g0.R, g0.x, g0.bnd, g0.bnd, 8,                  // 32-36 group part 0: records, dQ, pushes (fwd, bwd), tickets
+      g1.R, g1.x, g1.bnd, g1.bnd, 8,                  // 37-41 group part 1
+      size_t(c->ns) * c->ns * N * 4,                  // 42 surrogate J_C
+      size_t(sd.nslots) * 16,                         // 43 surrogate packed operands
+      size_t(sd.np) * 4,                              // 44 surrogate FP32 parameters
+      size_t(2 * sd.n_in + 1) * 8,                    // 45 surrogate scales
+      size_t(4) * c->ni * TR_N * 8,                   // 46 sweep trace
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -246,7 +267,7 @@ int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
   c->run = r;
   c->ns = mm->ns;
   c->nt = mm->two_temp ? 2 : 1;
-  c->strip_w = mm->ns <= 11 ? 64 : 16;  // widest compiled strip (fewest strip boundaries)
+  c->group_c = 1;  // persistent group kernels
   c->has_mech = true;
   c->has_fs = false;
   c->bound = false;
@@ -296,17 +317,23 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.hist = D(26);
   w.b = b + L.off[27]; w.dqs = b + L.off[28]; w.dq = b + L.off[29]; w.Dinv = b + L.off[30];
   w.flags = reinterpret_cast<int *>(b + L.off[31]);
-  w.state = b + L.off[32];
-  w.face = b + L.off[33];
-  w.bnd = b + L.off[34];
-  w.sync = reinterpret_cast<int *>(b + L.off[35]);
-  w.sur.J = reinterpret_cast<float *>(b + L.off[36]);
-  w.sur.P = reinterpret_cast<const u16x8 *>(b + L.off[37]);
-  w.sur.p = reinterpret_cast<const float *>(b + L.off[38]);
-  w.sur.scales = reinterpret_cast<const double *>(b + L.off[39]);
+  for (int q = 0; q < 2; ++q) {
+    const int o = 32 + 5 * q;
+    GroupBufs &gb = w.grp[q];
+    gb.R = b + L.off[o];
+    gb.x = b + L.off[o + 1];
+    gb.bnd[0] = b + L.off[o + 2];
+    gb.bnd[1] = b + L.off[o + 3];
+    gb.tickets = reinterpret_cast<int *>(b + L.off[o + 4]);
+  }
+  w.sur.J = reinterpret_cast<float *>(b + L.off[42]);
+  w.sur.P = reinterpret_cast<const u16x8 *>(b + L.off[43]);
+  w.sur.p = reinterpret_cast<const float *>(b + L.off[44]);
+  w.sur.scales = reinterpret_cast<const double *>(b + L.off[45]);
+  c->trace_buf = reinterpret_cast<long long *>(b + L.off[46]);
+  w.trace = c->trace > 0 ? c->trace_buf : nullptr;
   c->has_sur = false;
-  w.strip_w = c->strip_w;
-  w.pub_every = c->pub_every;
+  w.group_c = c->group_c;
   w.spin_limit = 4000000;
   w.nblk_cell = (c->N + 255) / 256;
   w.hist_max = HIST_MAX;
@@ -571,23 +598,22 @@ int csi_prim_to_cons(csi_ctx *c, int n, const double *rho_s, const double *u, co
   return CSI_OK;
 }
 
-int csi_set_sweep(csi_ctx *c, int width, int publish_every) {
+int csi_set_sweep(csi_ctx *c, int schedule) {
   if (!c) return CSI_ERR_ARG;
-  if (width != 0 && width != 16 && width != 64) return c->fail(CSI_ERR_ARG, "sweep width must be 0, 16 or 64");
-  if (width == 64 && c->ns > 11) return c->fail(CSI_ERR_UNSUPPORTED, "64-column strips are compiled for ns <= 11");
-  if (publish_every < 1 || publish_every > 64) return c->fail(CSI_ERR_ARG, "publish interval must be 1..64");
-  c->strip_w = width;
-  c->w.strip_w = width;
-  c->pub_every = publish_every;
-  c->w.pub_every = publish_every;
+  if (schedule != 0 && schedule != 1) return c->fail(CSI_ERR_ARG, "sweep schedule must be 0 or 1");
+  c->group_c = schedule;
+  c->w.group_c = schedule;
+  c->last_mode = -1;  // the records of the last operator are in the old layout
   c->has_res = false;
   c->has_dq = false;
   return CSI_OK;
 }
 
 int csi_set_timing(csi_ctx *c, int on) {
-  if (!c) return CSI_ERR_ARG;
+  if (!c || on < 0 || on > 2) return CSI_ERR_ARG;
   c->timing = on != 0;
+  c->trace = on == 2;
+  c->w.trace = c->trace && c->trace_buf ? c->trace_buf : nullptr;
   return CSI_OK;
 }
 
@@ -604,26 +630,114 @@ int csi_norm_history(csi_ctx *c, int n, double *hist) {
   return hip_check(c, hipMemcpy(hist, c->w.hist, size_t(2) * n * 8, hipMemcpyDeviceToHost), "history");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Sweep records and results of the last implicit operator, returned cell-major
+// as [field][N]: "b" (RHS) and "dqs" / "dq" nsol fields; "Dinv" coupled
+// [nb*nb] (row-major D^-1), split [nf*nf + ns*ns] (dense flow inverse, then
+// the species inverse).  Reads the cell-major arrays of the hyperplane
+// schedule or un-permutes the step-blocked group records.
+int get_records(csi_ctx *c, const std::string &n, double *out, size_t count) {
+  const size_t N = c->N;
+  const bool coupled = c->last_mode == CSI_COUPLED;
+  const int nsol = coupled ? c->nb() : c->nsplit();
+  const int nf = c->nf(), ns = c->ns, nb = c->nb();
+  const bool dinv = n == "Dinv";
+  const size_t F = dinv ? (coupled ? size_t(nb) * nb : size_t(nf) * nf + size_t(ns) * ns) : size_t(nsol);
+  if (count < F * N) return c->fail(CSI_ERR_ARG, "buffer too small for " + n);
+  const size_t esz = c->last_prec == CSI_MIXED ? 4 : 8;
+  auto fetch = [&](const void *src, size_t cnt, std::vector<double> &dst) -> int {
+    std::vector<char> tmp(cnt * esz);
+    int rc = hip_check(c, hipMemcpy(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost), "get");
+    if (rc) return rc;
+    dst.resize(cnt);
+    for (size_t k = 0; k < cnt; ++k)
+      dst[k] = esz == 4 ? double(reinterpret_cast<const float *>(tmp.data())[k]) : reinterpret_cast<const double *>(tmp.data())[k];
+    return CSI_OK;
+  };
+  std::vector<double> h;
+  if (c->group_c == 0) {
+    if (!dinv) {
+      const void *src = n == "b" ? c->w.b : n == "dqs" ? c->w.dqs : c->w.dq;
+      if (int rc = fetch(src, size_t(nsol) * N, h)) return rc;
+      std::copy(h.begin(), h.end(), out);
+      return CSI_OK;
+    }
+    const size_t cm = coupled ? size_t(nb) * nb : 6 + size_t(ns) * ns;
+    if (int rc = fetch(c->w.Dinv, cm * N, h)) return rc;
+    if (coupled) { std::copy(h.begin(), h.end(), out); return CSI_OK; }
+    // closed-form flow block (x_k = r_k d0, k < 4; x_4 = (r_4 + sum_k a_k x_k) p) as a dense inverse
+    std::fill(out, out + size_t(nf) * nf * N, 0.0);
+    for (size_t p = 0; p < N; ++p) {
+      const double d0 = h[p];
+      for (int r = 0; r < 4; ++r) out[size_t(r * nf + r) * N + p] = d0;
+      if (nf == 5) {
+        const double piv = h[5 * N + p];
+        for (int k = 0; k < 4; ++k) out[size_t(4 * nf + k) * N + p] = h[(1 + k) * N + p] * d0 * piv;
+        out[size_t(4 * nf + 4) * N + p] = piv;
+      }
+    }
+    std::copy(h.begin() + 6 * N, h.end(), out + size_t(nf) * nf * N);
+    return CSI_OK;
+  }
+  // group schedule
+  const int nparts = coupled ? 1 : 2;
+  size_t fo = 0;  // first output field of the part
+  for (int q = 0; q < nparts; ++q) {
+    const PartShape ps = part_shape(q == 1 ? PART_SPECIES : coupled ? PART_COUPLED : PART_FLOW, ns, c->nt);
+    const int G = ps.G;
+    const GroupMap m = group_map(c->ni, c->nj, ps, 64 / G, int(esz));
+    const GroupBufs &gb = c->w.grp[q];
+    const bool res = n == "dq";
+    if (int rc = fetch(res ? gb.x : gb.R, size_t(m.nblk) * (res ? m.Lw : m.RW), h)) return rc;
+    const int nout = dinv ? G * G : G;
+    for (int j = 0; j < c->nj; ++j)
+      for (int i = 0; i < c->ni; ++i) {
+        int cc;
+        const long blk = group_blk(m, i, j, cc);
+        const size_t p = size_t(j) * c->ni + i;
+        for (int f = 0; f < nout; ++f) {
+          const int r = dinv ? f / G : f, col = dinv ? f % G : 0;
+          const long k = dinv ? m.drow(blk, col, cc, r) : n == "b" ? m.lane(blk, 0, cc, r)
+                                                       : n == "dqs" ? m.xs(blk, cc, r) : m.res(blk, cc, r);
+          out[(fo + f) * N + p] = h[size_t(k)];
+        }
+      }
+    fo += nout;
+  }
+  return CSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
   if (!c || !name || !out) return CSI_ERR_ARG;
   if (!c->bound) return c->fail(CSI_ERR_STATE, "not bound");
   std::string n(name);
   const size_t N = c->N;
   const double *src = nullptr;
-  const void *rsrc = nullptr;
   size_t cnt = 0;
   size_t NP = size_t(c->ni + 2) * (c->nj + 2);
-  int nsol = c->last_mode == CSI_COUPLED ? c->nb() : c->nsplit();
   if (n == "R") { src = c->w.R; cnt = c->nv() * N; }
   else if (n == "dtau") { src = c->w.dtau; cnt = N; }
   else if (n == "src") { src = c->w.src; cnt = c->nv() * N; }
   else if (n == "qw") { src = c->w.qw; cnt = c->ni; }
-  else if (n == "b") { rsrc = c->w.b; cnt = nsol * N; }
-  else if (n == "dqs") { rsrc = c->w.dqs; cnt = nsol * N; }
-  else if (n == "dq") { rsrc = c->w.dq; cnt = nsol * N; }
-  else if (n == "Dinv") {
-    rsrc = c->w.Dinv;
-    cnt = (c->last_mode == CSI_COUPLED ? size_t(c->nb()) * c->nb() : 6 + size_t(c->ns) * c->ns) * N;
+  else if (n == "b" || n == "dqs" || n == "dq" || n == "Dinv") {
+    if (c->last_mode < 0 || c->last_prec < 0) return c->fail(CSI_ERR_STATE, "no implicit operator applied yet");
+    return get_records(c, n, out, count);
+  } else if (n == "sweep_trace") {
+    if (!c->trace) return c->fail(CSI_ERR_STATE, "sweep trace is off");
+    const size_t cntt = size_t(4) * c->ni * TR_N;
+    if (count < cntt) return c->fail(CSI_ERR_ARG, "buffer too small for sweep_trace");
+    std::vector<long long> tmp(cntt);
+    int rc = hip_check(c, hipMemcpy(tmp.data(), c->trace_buf, cntt * 8, hipMemcpyDeviceToHost), "get");
+    if (rc) return rc;
+    for (size_t k = 0; k < cntt; ++k) out[k] = double(tmp[k]);
+    return CSI_OK;
   } else if (n == "Jsur") {
     const size_t cntj = size_t(c->ns) * c->ns * N;
     if (count < cntj) return c->fail(CSI_ERR_ARG, "buffer too small for Jsur");
@@ -645,32 +759,8 @@ int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
     return c->fail(CSI_ERR_ARG, "unknown array " + n);
   }
   if (count < cnt) return c->fail(CSI_ERR_ARG, "buffer too small for " + n);
-  if (src) return hip_check(c, hipMemcpy(out, src, cnt * 8, hipMemcpyDeviceToHost), "get");
-  // sweep records: cell-major or strip layout, FP64 or FP32
-  const size_t rows = cnt / N;
-  size_t stride = N;
-  StripMap sm{};
-  if (c->strip_w > 0) {
-    sm = strip_map(c->ni, c->nj, c->strip_w);
-    stride = sm.LEN;
-  }
-  const size_t esz = c->last_prec == CSI_MIXED ? 4 : 8;
-  // array width (fields per record) of the step-blocked layout
-  const int F = n == "Dinv" ? std::max(c->nb() * c->nb(), 6 + c->ns * c->ns) : c->nsplit();
-  std::vector<char> tmp(size_t(F) * stride * esz);
-  int rc = hip_check(c, hipMemcpy(tmp.data(), rsrc, tmp.size(), hipMemcpyDeviceToHost), "get");
-  if (rc) return rc;
-  for (size_t r_ = 0; r_ < rows; ++r_)
-    for (int j = 0; j < c->nj; ++j)
-      for (int i = 0; i < c->ni; ++i) {
-        size_t k = c->strip_w > 0 ? size_t(rec_idx(strip_pos(sm, i, j), i % c->strip_w, F, int(r_), c->strip_w))
-                                  : r_ * stride + size_t(j) * c->ni + i;
-        out[r_ * N + size_t(j) * c->ni + i] =
-            esz == 4 ? double(reinterpret_cast<const float *>(tmp.data())[k]) : reinterpret_cast<const double *>(tmp.data())[k];
-      }
-  return CSI_OK;
+  return hip_check(c, hipMemcpy(out, src, cnt * 8, hipMemcpyDeviceToHost), "get");
 }
-
 
 // ------------------------------------------------------------ surrogate network
 }  // extern "C"

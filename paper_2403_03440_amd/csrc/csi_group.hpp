@@ -1,0 +1,540 @@
+// LU-SGS sweeps with one group of lanes per cell.
+//
+// The i+j hyperplane order of the sweeps (paper Section 2.2, forward
+// (D+L) dQ* = RHS and backward (D+U) dQ = D dQ*) is executed strip by strip:
+// one workgroup per strip of C columns.  Each cell of the strip is owned by a
+// group of G lanes of the compute wavefront, one lane per unknown of the swept
+// part (G = nb coupled, nf flow part, ns species part; C <= 64 / G).  At step d
+// the group of column c owns cell (i0 + c, d - c); its west neighbour was
+// computed by the previous group one step earlier and its south neighbour by
+// the same group one step earlier.  A step of lane k is:
+//   r_k = b_k - pushW_k - pushS_k,
+//   x_k = sum_m (D^-1)_km r_m          (r gathered from the group's lanes),
+//   the two pushes O x of this cell towards its east and north neighbours,
+//   component k (the flux Jacobian-vector product needs the whole x, gathered
+//   again; the species operator is a scalar times x_k).
+// The pushes move to the next group through a cross-lane permute.
+//
+// A step is a short chain of dependent arithmetic, so the sweep is bound by
+// latency, not bandwidth.  The workgroup therefore has three wavefronts, so
+// that the compute wave never waits for global memory:
+//   wave 0  computes; it reads its step records from an LDS ring;
+//   wave 1  streams the step records into the ring with global-to-LDS copies
+//           (whole KiB per instruction), up to a ring of DEPTH steps ahead;
+//   wave 2  takes the pushes that cross the strip boundary (written by the
+//           neighbouring strip's compute wave) and hands them over in LDS.
+// A boundary push is its own ready flag: its slot is filled with an all-ones
+// pattern (a NaN that arithmetic never produces) before the sweep, and the
+// consumer polls the slot until it holds a value, so the producer never waits
+// for its stores.  Strips are taken in dependency order from an atomic ticket
+// (every strip waits only on strips that already run, so there is no
+// deadlock); every wait is bounded and a shared abort flag makes every wave
+// exit.  In the split form the flow and species parts are independent
+// (Section 2.3 discards the cross terms) and run in separate workgroups.
+#pragma once
+#include "csi_sweep.hpp"
+
+namespace csi {
+
+// device buffers of one part (inside the workspace)
+struct GroupBufs {
+  void *R;        // step records (RT), see the record layout
+  void *x;        // backward results dQ (RT) [blk][C G]
+  void *bnd[2];   // boundary pushes of the forward / backward sweep, RT [nstrip][nj][G]
+  int *tickets;   // [2] strip tickets of the forward / backward sweep
+};
+struct GroupPart {
+  GroupBufs b;
+  int C;          // cells per wave (64 / G)
+};
+struct GroupArgs {
+  GroupPart part[2];  // coupled or flow; species
+  int *abort_flag;
+  long spin_limit;
+  long long *trace;   // optional per-strip trace [part][strip][TR_N] of this sweep
+};
+// per-strip trace: wall clock (100 MHz) at the compute wave's start and end,
+// spins of the compute wave on step records and on boundary pushes, spins of
+// the copy wave on free ring slots and of the boundary wave on pushes
+enum { TR_T0 = 0, TR_T1, TR_REC, TR_BND, TR_COPY, TR_POLL, TR_N = 8 };
+
+// ring geometry of a part: KB KiB per step record, DEPTH slots, at most LAG
+// steps of copies in flight (LAG KB copy instructions <= 60: the vector
+// memory counter has 6 bits)
+template <int NS, int NT, typename RT, int P> struct GPipe {
+  static constexpr PartShape S = part_shape(P, NS, NT);
+  static constexpr int G = S.G;
+  static constexpr int KB = group_kib(S, sizeof(RT));
+  static constexpr int DEPTH = 128 / KB < 16 ? 128 / KB : 16;
+  static constexpr int LAG = 60 / KB < DEPTH - 1 ? 60 / KB : DEPTH - 1;
+  static constexpr size_t RING = size_t(DEPTH) * KB * 1024;
+  static constexpr size_t LDS = RING + size_t(DEPTH) * G * sizeof(RT);
+};
+template <int NS, int NT, typename RT, int MODE> constexpr size_t group_lds_bytes() {
+  if (MODE == 0) return GPipe<NS, NT, RT, PART_COUPLED>::LDS;
+  const size_t a = GPipe<NS, NT, RT, PART_FLOW>::LDS, b = GPipe<NS, NT, RT, PART_SPECIES>::LDS;
+  return a > b ? a : b;
+}
+
+// ------------------------------------------------------------ synchronisation
+__device__ __forceinline__ bool aborted(const int *f) {
+  return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+__device__ __forceinline__ void set_abort(int *f) {
+  __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// LDS counters shared by the three waves (compute and boundary waves)
+__device__ __forceinline__ int lds_get(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_set(int *p, int v) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// spin until *p >= need; seen receives the value read, spins the number of
+// extra reads; a waiting wave sleeps `sleep` units between reads (0: the
+// wave on the critical path, 1: a wave that runs ahead).  False on timeout /
+// abort.
+__device__ __forceinline__ bool lds_wait(const int *p, int need, int *abort_flag, long spin_limit, long &spins,
+                                         int &seen, int sleep) {
+  long n = 0;
+  while ((seen = lds_get(p)) < need) {
+    if (++n > spin_limit) { set_abort(abort_flag); return false; }
+    if ((n & 255) == 0 && aborted(abort_flag)) return false;
+    if (sleep) __builtin_amdgcn_s_sleep(1);
+  }
+  spins += n;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return true;
+}
+
+// The copy wave's own LDS accesses are written in assembly (each waits for
+// its result in the same block): the compiler would otherwise make them wait
+// for every copy still in flight, since copies and reads share the LDS.
+__device__ __forceinline__ unsigned lds_addr(const void *p) {
+  // (a C-style cast converts the generic pointer to a 32-bit LDS address)
+  return unsigned(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char *)(p)));
+}
+__device__ __forceinline__ int lds_get_asm(const int *p) {
+  int v;
+  asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(lds_addr(p)) : "memory");
+  return v;
+}
+__device__ __forceinline__ void lds_set_asm(int *p, int v) {
+  asm volatile("ds_write_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : : "v"(lds_addr(p)), "v"(v) : "memory");
+}
+// s_waitcnt immediate that waits for the vector memory counter only
+constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// boundary pushes: all-ones = empty slot
+template <typename RT> struct UBits;
+template <> struct UBits<float> { using T = unsigned int; };
+template <> struct UBits<double> { using T = unsigned long long; };
+template <typename RT> __device__ __forceinline__ void put_push(RT *p, RT v) {
+  using U = typename UBits<RT>::T;
+  __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename RT>
+__device__ __forceinline__ bool take_push(const RT *p, RT &v, int *abort_flag, long spin_limit, long &spins) {
+  using U = typename UBits<RT>::T;
+  long &n = spins;
+  U u;
+  while ((u = __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == ~U(0)) {
+    if (++n > spin_limit) { set_abort(abort_flag); return false; }
+    if ((n & 63) == 0 && aborted(abort_flag)) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  v = __builtin_bit_cast(RT, u);
+  return true;
+}
+
+// ------------------------------------------------------------ step arithmetic
+// The step arithmetic is written with explicit fused multiply-adds and
+// contraction off, so that every cell gets the same rounding whatever its
+// position in the unrolled loop (results do not depend on C).
+template <typename RT> __device__ __forceinline__ RT fmad(RT a, RT b, RT c) { return fma(a, b, c); }
+
+// compile-time layout of one step block (C = 64 / G cells per wave)
+template <int NS, int NT, int P> struct GLayout {
+  static constexpr PartShape S = part_shape(P, NS, NT);
+  static constexpr int G = S.G, C = 64 / G, Lw = G * C, FL = S.FL, FC = S.FC;
+  static constexpr int OX = FL * Lw, OD = OX + Lw, OC = OD + G * Lw;  // dQ*, D^-1 rows, cell fields
+};
+
+// per-step record of one lane
+template <int NS, int NT, typename RT, int P, bool FWD> struct GRec {
+  using Gp = GPart<NS, NT, P>;
+  using Ly = GLayout<NS, NT, P>;
+  static constexpr int G = Gp::G;
+  RT b;        // forward: RHS b_k; backward: dQ*_k
+  RT ca;       // JVP parts: coefficient of a in component k
+  RT Dr[G];    // row k of D^-1
+  RT u, v;     // cell velocity
+  RT f[6];     // push 1 (mx, my, c), push 2 (mx, my, c)
+  RT w[Gp::JVP ? G : 1];  // dp weights (JVP parts)
+
+  // from one step block in LDS: L = block + k C + c (lane fields), Q = block + OC + c (cell fields)
+  __device__ __forceinline__ void load(const RT *L, const RT *Q) {
+    b = FWD ? L[0] : L[Ly::OX];
+    if (Gp::JVP) ca = L[Ly::Lw];
+#pragma unroll
+    for (int q = 0; q < G; ++q) Dr[q] = L[Ly::OD + q * Ly::Lw];
+    u = Q[CF_U * Ly::C];
+    v = Q[CF_V * Ly::C];
+    constexpr int p0 = CF_PUSH + (FWD ? 0 : 6);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = Q[(p0 + q) * Ly::C];
+    if (Gp::JVP) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) w[q] = Q[(CF_W + q) * Ly::C];
+    }
+  }
+};
+
+// value of v in the lane whose byte address (4 x lane) is addr
+__device__ __forceinline__ float gather(float v, int addr) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double gather(double v, int addr) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, int(u & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, int(u >> 32));
+  return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+// cross-lane moves by one lane (DPP wavefront shifts; the vacated lane reads 0):
+// UP: lane l takes lane l - 1, else lane l + 1
+template <bool UP> __device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, UP ? 0x138 : 0x130, 0xF, 0xF, true);
+}
+template <bool UP> __device__ __forceinline__ float lane_move(float v) {
+  return __builtin_bit_cast(float, dpp_move<UP>(__builtin_bit_cast(int, v)));
+}
+template <bool UP> __device__ __forceinline__ double lane_move(double v) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = dpp_move<UP>(int(u & 0xffffffffll)), hi = dpp_move<UP>(int(u >> 32));
+  return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+
+// component k of the push O x for one face (m = half-length-scaled normal of
+// the receiving cell, c = radius coefficient): JVP parts
+//   o_k = un x'_k + ca_k a + cp_k dp + [k = 0] dmn - c x_k,
+//   un = u.m, dmn = x_1 m_x + x_2 m_y, a = dmn - un x_0, dp = w.x,
+//   x'_k = x_k (k > 0), cp = (0, m_x, m_y, un, 0, ...);
+// species part: (u.m - c) x_k.
+template <int NS, int NT, typename RT, int P, bool FWD>
+__device__ __forceinline__ RT push_comp(const GRec<NS, NT, RT, P, FWD> &R, int q, int k, RT xk, const RT *xall,
+                                        RT dp) {
+#pragma clang fp contract(off)
+  const RT mx = R.f[3 * q], my = R.f[3 * q + 1], c = R.f[3 * q + 2];
+  const RT un = fmad(R.v, my, R.u * mx);
+  if (P == PART_SPECIES) return (un - c) * xk;
+  const RT dmn = fmad(xall[2], my, xall[1] * mx);
+  const RT a = fmad(-un, xall[0], dmn);
+  RT o = fmad(-c, xk, R.ca * a);
+  o = k == 0 ? o + dmn : fmad(un, xk, o);
+  const RT cp = k == 1 ? mx : k == 2 ? my : k == 3 ? un : RT(0);
+  return fmad(cp, dp, o);
+}
+
+// ------------------------------------------------------------ the three waves
+struct GroupSync {
+  int strip;      // strip of this workgroup
+  int rec_ready;  // step records in the ring (copy wave)
+  int bnd_ready;  // boundary pushes in LDS (boundary wave)
+  int consumed;   // steps whose ring slots the compute wave has read
+};
+
+// wave 1: step records of the strip, in sweep order, into the LDS ring
+template <int KB, int DEPTH, int LAG>
+__device__ __forceinline__ long copy_wave(const char *R, long blk0, int dir, int NSTEP, char *ring, GroupSync &sy,
+                                          int *abort_flag, long spin_limit) {
+  const int lane = threadIdx.x & 63;
+  int pub = 0, seen = 0, slot = 0;
+  long spins = 0;
+  for (int e = 0; e < NSTEP; ++e) {
+    if (e >= DEPTH && seen < e - DEPTH + 1) {
+      // a full ring ahead of the compute wave: publish what has landed and
+      // wait for the oldest slot to be read
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      pub = e;
+      lds_set_asm(&sy.rec_ready, pub);
+      long n = 0;
+      while ((seen = lds_get_asm(&sy.consumed)) < e - DEPTH + 1) {
+        if (++n > spin_limit) { set_abort(abort_flag); return spins; }
+        if ((n & 255) == 0 && aborted(abort_flag)) return spins;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      spins += n;
+    }
+    const char *src = R + (blk0 + long(dir) * e) * (KB * 1024L) + lane * 16;
+    char *dst = ring + slot * (KB * 1024);
+#pragma unroll
+    for (int q = 0; q < KB; ++q)
+      __builtin_amdgcn_global_load_lds(src + q * 1024,
+                                       (__attribute__((address_space(3))) void *)(dst + q * 1024), 16, 0, 0);
+    if (++slot == DEPTH) slot = 0;
+    if (e >= LAG) {
+      // copies of step e - LAG have landed once at most LAG steps of copies are in flight
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(LAG * KB));
+      if (e - LAG + 1 > pub) {
+        pub = e - LAG + 1;
+        lds_set_asm(&sy.rec_ready, pub);
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+  lds_set_asm(&sy.rec_ready, NSTEP);
+  return spins;
+}
+
+// wave 2: the G pushes that enter the strip at each step, from the
+// neighbouring strip (slot idx(e) < 0: no push at step e)
+template <typename RT, int G, int DEPTH, typename IDX>
+__device__ __forceinline__ long boundary_wave(const RT *bnd, IDX idx, bool any, int NSTEP, RT *bring, GroupSync &sy,
+                                              int *abort_flag, long spin_limit) {
+  const int lane = threadIdx.x & 63;
+  if (!any) {  // a strip at the edge of the grid takes no pushes
+    lds_set(&sy.bnd_ready, NSTEP);
+    return 0;
+  }
+  int slot = 0, seen = 0;
+  bool ok = true;
+  long spins = 0, slot_spins = 0;
+  for (int e = 0; e < NSTEP; ++e) {
+    const long at = idx(e);
+    if (at >= 0) {
+      if (e >= DEPTH && seen < e - DEPTH + 1) {
+        if (!lds_wait(&sy.consumed, e - DEPTH + 1, abort_flag, spin_limit, slot_spins, seen, 1)) return spins;
+      }
+      if (lane < G) {
+        RT v = RT(0);
+        if (ok) ok = take_push(bnd + at + lane, v, abort_flag, spin_limit, spins);
+        bring[slot * G + lane] = v;
+      }
+    }
+    if (++slot == DEPTH) slot = 0;
+    lds_set(&sy.bnd_ready, e + 1);
+  }
+  return spins;
+}
+
+// spin until *p >= need (rare path of the compute wave); returns the value
+// read, or sets the abort flag and clears live on timeout / abort
+__device__ __forceinline__ int lds_spin(const int *p, int need, int *abort_flag, long spin_limit, long &spins,
+                                        bool &live) {
+  int v = lds_get(p);
+  long n = 0;
+  while (v < need && live) {
+    ++n;
+    if (n > spin_limit || ((n & 1023) == 0 && aborted(abort_flag))) {
+      set_abort(abort_flag);
+      live = false;
+    }
+    v = lds_get(p);
+  }
+  spins += n;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return v;
+}
+
+// wave 0: the sweep recurrence.  Lane (c, k) = k C + c; the push of column c
+// reaches column c + 1 (forward, east) or c - 1 (backward, west) by a one-lane
+// move, the north / south push stays in the lane for the next step.  The step
+// records are read from the ring one step ahead.  After a timeout the wave
+// stops waiting and runs to the end (its results are then discarded).
+template <int NS, int NT, typename RT, int P, bool FWD>
+__device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, const GroupPart &gp,
+                                             const GroupMap &m, int s, const RT *ring, const RT *bring, GroupSync &sy,
+                                             long &rsp, long &bsp) {
+#pragma clang fp contract(off)
+  using Pp = GPipe<NS, NT, RT, P>;
+  using Ly = GLayout<NS, NT, P>;
+  using R = GRec<NS, NT, RT, P, FWD>;
+  constexpr int G = Pp::G, DEPTH = Pp::DEPTH, SLOT = Pp::KB * 1024 / int(sizeof(RT)), C = Ly::C;
+  constexpr bool JVP = GPart<NS, NT, P>::JVP;
+  const int lane = threadIdx.x & 63;
+  const int NSTEP = m.NSTEP;
+  const int k = lane / C, c = lane - k * C;
+  const bool lane_ok = k < G;
+  const int kk = lane_ok ? k : G - 1;  // idle lanes read (and discard) the last component
+  const int i = s * C + c;
+  const bool col_ok = lane_ok && i < g.ni;
+  int gaddr[G];  // byte addresses of the group's lanes (q C + c)
+#pragma unroll
+  for (int q = 0; q < G; ++q) gaddr[q] = (q * C + c) * 4;
+  RT *out = reinterpret_cast<RT *>(FWD ? gp.b.R : gp.b.x);
+  RT *bnd = reinterpret_cast<RT *>(gp.b.bnd[FWD ? 0 : 1]);
+  const long b0 = long(s) * NSTEP;
+  // the column that takes a push from the neighbouring strip
+  constexpr int edge = FWD ? 0 : C - 1;
+  const bool has_nb = FWD ? s > 0 : s < m.nstrip - 1;
+  const bool h1 = FWD ? i > 0 : i + 1 < g.ni, s1 = FWD ? i + 1 < g.ni : i > 0;
+  const bool send_nb = c == C - 1 - edge && (FWD ? i + 1 < g.ni : s > 0);
+  const int lofs = kk * C + c, cofs = Ly::OC + c;
+  bool live = true;
+  int rec_seen = lds_spin(&sy.rec_ready, 1, a.abort_flag, a.spin_limit, rsp, live);
+  int bnd_seen = 0;
+  R A, B;
+  A.load(ring + lofs, ring + cofs);
+  RT in1 = RT(0), in2 = RT(0);  // pushes from the west / south (forward), east / north (backward)
+  int slot = 0;
+  auto step = [&](int e, R &cur, R &nxt) {
+    const int d = FWD ? e : NSTEP - 1 - e;
+    const int j = d - c;
+    const int jb = d - edge;
+    if (has_nb && jb >= 0 && jb < g.nj) {
+      if (bnd_seen <= e) bnd_seen = lds_spin(&sy.bnd_ready, e + 1, a.abort_flag, a.spin_limit, bsp, live);
+      const RT v = bring[slot * G + kk];
+      in1 = c == edge ? v : in1;
+    }
+    // r = b -/+ pushes, gathered over the group
+    const bool h2 = FWD ? j > 0 : j + 1 < g.nj;
+    RT r = FWD ? cur.b : RT(0);
+    if (FWD) {
+      r = h1 ? r - in1 : r;
+      r = h2 ? r - in2 : r;
+    } else {
+      r = h1 ? r + in1 : r;
+      r = h2 ? r + in2 : r;
+    }
+    RT rg[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) rg[q] = gather(r, gaddr[q]);
+    // the next step's record, behind the gather in the LDS queue
+    const int nslot = slot + 1 == DEPTH ? 0 : slot + 1;
+    if (e + 1 < NSTEP) {
+      if (rec_seen <= e + 1) rec_seen = lds_spin(&sy.rec_ready, e + 2, a.abort_flag, a.spin_limit, rsp, live);
+      const RT *S = ring + nslot * SLOT;
+      nxt.load(S + lofs, S + cofs);
+    }
+    lds_set(&sy.consumed, e + 1);
+    slot = nslot;
+    RT y = cur.Dr[0] * rg[0];
+#pragma unroll
+    for (int q = 1; q < G; ++q) y = fmad(cur.Dr[q], rg[q], y);
+    const RT x = FWD ? y : cur.b - y;
+    const bool s2 = FWD ? j + 1 < g.nj : j > 0;
+    RT p1, p2;
+    if (JVP) {
+      RT xall[G];
+      RT dp = RT(0);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        xall[q] = gather(x, gaddr[q]);
+        dp = q == 0 ? cur.w[0] * xall[0] : fmad(cur.w[q], xall[q], dp);
+      }
+      p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, k, x, xall, dp);
+      p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, k, x, xall, dp);
+    } else {
+      p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, k, x, nullptr, RT(0));
+      p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, k, x, nullptr, RT(0));
+    }
+    const bool active = col_ok && j >= 0 && j < g.nj;
+    p1 = active && s1 ? p1 : RT(0);
+    p2 = active && s2 ? p2 : RT(0);
+    if (active) {
+      out[FWD ? (b0 + d) * SLOT + Ly::OX + k * C + c : (b0 + d) * Ly::Lw + k * C + c] = x;
+      if (send_nb) put_push(bnd + (long(FWD ? s : s - 1) * g.nj + j) * G + k, p1);
+    }
+    in1 = lane_move<FWD>(p1);
+    in2 = p2;
+  };
+#pragma unroll 1
+  for (int e = 0; e < NSTEP; e += 2) {
+    step(e, A, B);
+    if (e + 1 < NSTEP) step(e + 1, B, A);
+  }
+}
+
+template <int NS, int NT, typename RT, int P, bool FWD>
+__device__ __forceinline__ void group_part(const Geo &g, const GroupArgs &a, int q, char *lds, GroupSync &sy) {
+  using Pp = GPipe<NS, NT, RT, P>;
+  constexpr int G = Pp::G;
+  const GroupPart &gp = a.part[q];
+  const GroupMap m = group_map(g.ni, g.nj, Pp::S, gp.C, sizeof(RT));
+  if (threadIdx.x == 0) {
+    sy.strip = FWD ? atomicAdd(gp.b.tickets, 1) : m.nstrip - 1 - atomicAdd(gp.b.tickets + 1, 1);
+    sy.rec_ready = 0;
+    sy.bnd_ready = 0;
+    sy.consumed = 0;
+  }
+  __syncthreads();
+  const int s = __builtin_amdgcn_readfirstlane(sy.strip);
+  if (s < 0 || s >= m.nstrip) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const RT *ring = reinterpret_cast<const RT *>(lds);
+  RT *bring = reinterpret_cast<RT *>(lds + Pp::RING);
+  const long b0 = long(s) * m.NSTEP;
+  long long *tr = a.trace ? a.trace + (long(q) * g.ni + s) * TR_N : nullptr;
+  const int lane = threadIdx.x & 63;
+  if (wave == 1) {
+    const long sp = copy_wave<Pp::KB, Pp::DEPTH, Pp::LAG>(reinterpret_cast<const char *>(gp.b.R),
+                                                          FWD ? b0 : b0 + m.NSTEP - 1, FWD ? 1 : -1, m.NSTEP, lds, sy,
+                                                          a.abort_flag, a.spin_limit);
+    if (tr && lane == 0) tr[TR_COPY] = sp;
+  } else if (wave == 2) {
+    const RT *bnd = reinterpret_cast<const RT *>(gp.b.bnd[FWD ? 0 : 1]);
+    const int nj = g.nj, C = m.C, NSTEP = m.NSTEP, last = m.nstrip - 1;
+    if (FWD) {
+      // west pushes of column 0: cell (i0, j = d), written by strip s - 1
+      const long sp = boundary_wave<RT, G, Pp::DEPTH>(
+          bnd, [=](int e) -> long { return s > 0 && e < nj ? (long(s - 1) * nj + e) * G : -1L; }, s > 0, NSTEP,
+          bring, sy, a.abort_flag, a.spin_limit);
+      if (tr && lane == 0) tr[TR_POLL] = sp;
+    } else {
+      // east pushes of column C - 1: cell (i0 + C - 1, j = d - C + 1), written by strip s + 1
+      const long sp = boundary_wave<RT, G, Pp::DEPTH>(
+          bnd,
+          [=](int e) -> long {
+            const int jl = NSTEP - 1 - e - (C - 1);
+            return s < last && jl >= 0 && jl < nj ? (long(s) * nj + jl) * G : -1L;
+          },
+          s < last, NSTEP, bring, sy, a.abort_flag, a.spin_limit);
+      if (tr && lane == 0) tr[TR_POLL] = sp;
+    }
+  } else {
+    const long long t0 = tr ? (long long)wall_clock64() : 0;
+    long rsp = 0, bsp = 0;
+    compute_wave<NS, NT, RT, P, FWD>(g, a, gp, m, s, ring, bring, sy, rsp, bsp);
+    if (tr && lane == 0) {
+      tr[TR_T0] = t0;
+      tr[TR_T1] = (long long)wall_clock64();
+      tr[TR_REC] = rsp;
+      tr[TR_BND] = bsp;
+    }
+  }
+}
+
+// One three-wave workgroup per strip and part.  Coupled: grid (nstrip);
+// split: grid (max nstrip, 2), y = 0 flow part, y = 1 species part.
+template <int NS, int NT, typename RT, int MODE, bool FWD>
+__global__ void __launch_bounds__(192) k_group_sweep(Geo g, GroupArgs a, const int *__restrict__ done) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ GroupSync sy;
+  if (done && *done) return;
+  if (MODE == 0) group_part<NS, NT, RT, PART_COUPLED, FWD>(g, a, 0, lds, sy);
+  else if (blockIdx.y == 0) group_part<NS, NT, RT, PART_FLOW, FWD>(g, a, 0, lds, sy);
+  else group_part<NS, NT, RT, PART_SPECIES, FWD>(g, a, 1, lds, sy);
+}
+
+// Before a sweep pair: clears the strip tickets and marks every boundary-push
+// slot empty (all-ones); nw: 32-bit words of each boundary array.
+struct GroupReset {
+  int *tickets[2];
+  unsigned *bnd[4];
+  long nw[4];
+};
+template <int NS>
+__global__ void __launch_bounds__(256) k_group_reset(GroupReset r, const int *__restrict__ done) {
+  if (done && *done) return;
+  const long t = long(blockIdx.x) * blockDim.x + threadIdx.x, stride = long(gridDim.x) * blockDim.x;
+  if (t < 2) {
+    if (r.tickets[0]) r.tickets[0][t] = 0;
+    if (r.tickets[1]) r.tickets[1][t] = 0;
+  }
+  for (int q = 0; q < 4; ++q)
+    for (long k = t; k < r.nw[q]; k += stride) r.bnd[q][k] = ~0u;
+}
+
+}  // namespace csi

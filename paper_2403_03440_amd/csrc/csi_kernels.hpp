@@ -381,43 +381,81 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
   return true;
 }
 
-// ------------------------------------------------ sweep record layout
-// Strip map of the persistent sweeps (one wavefront per strip of W columns;
-// at step d lane l owns cell (i0 + l, d - l)) and the step-blocked layout of
-// the per-cell sweep records: all cells of one strip step contiguous,
-// field-major inside the step,
-//   element (field f of F, strip s, step d, lane l) at ((s NSTEP + d) F + f) W + l.
-struct StripMap {
-  int W, NSTEP, nstrip;
-  long LEN;
+// ----------------------------------------------- group-schedule record layout
+// The sweeps give each cell a group of G lanes (one per unknown of the swept
+// part) and each wavefront a strip of C <= 64 / G columns.  Records are
+// stored in step blocks blk = s NSTEP + d (strip s, step d = i - i0 + j,
+// NSTEP = nj + C - 1); one block is contiguous so that a sweep wave can copy
+// it to LDS with whole-KiB transfers:
+//   lane fields  [F_L][G C]   RHS b_k, coefficient of a in the JVP (lane (c, k) at k C + c)
+//   dQ*          [G C]        written by the forward sweep for the backward sweep
+//   D^-1 rows    [G][G C]     (D^-1)_km at lane (c, k), field m
+//   cell fields  [F_C][C]     u, v, push normals and radii, dp weights
+// padded to a whole number of KiB (the size at C = 64 / G, so the stride does
+// not depend on C).  The backward results dQ are a separate array [blk][G C].
+// Lanes are component-major (k C + c), so that the push of column c reaches
+// column c + 1 (same component) one lane up.
+
+// parts of the implicit operator swept by one wavefront
+enum { PART_COUPLED = 0, PART_FLOW = 2, PART_SPECIES = 3 };
+enum { CF_U = 0, CF_V = 1, CF_PUSH = 2, CF_W = 14 };
+
+// lanes per cell, lane fields, cell fields of a part
+struct PartShape {
+  int G, FL, FC;
+};
+__host__ __device__ constexpr PartShape part_shape(int part, int ns, int nt) {
+  const int nf = nt == 2 ? 5 : 4, nb = nf + ns - 1;
+  return part == PART_COUPLED ? PartShape{nb, 2, 14 + nb} : part == PART_FLOW ? PartShape{nf, 2, 14 + nf}
+                                                                               : PartShape{ns, 1, 14};
+}
+// KiB per step record (element size esz)
+__host__ __device__ constexpr int group_kib(PartShape p, int esz) {
+  const int CM = 64 / p.G;
+  const long used = long(p.FL + 1 + p.G) * CM * p.G + long(p.FC) * CM;
+  return int((used * esz + 1023) / 1024);
+}
+
+template <int NS, int NT, int P> struct GPart {
+  static constexpr PartShape S = part_shape(P, NS, NT);
+  static constexpr int G = S.G, FL = S.FL, FC = S.FC;
+  static constexpr int CMAX = 64 / G;          // cells per wave
+  static constexpr bool JVP = P != PART_SPECIES;
 };
 
-__host__ __device__ inline StripMap strip_map(int ni, int nj, int W) {
-  StripMap s;
-  s.W = W;
-  s.NSTEP = nj + W - 1;
-  s.nstrip = (ni + W - 1) / W;
-  s.LEN = long(s.nstrip) * s.NSTEP * W;
-  return s;
-}
-// cell (i, j) -> step-major cell position (s NSTEP + d) W + l, d = j + l
-__host__ __device__ inline long strip_pos(const StripMap &sm, int i, int j) {
-  int s = i / sm.W, l = i - s * sm.W;
-  return (long(s) * sm.NSTEP + j + l) * sm.W + l;
-}
-// element of field f (of F) of the record at cell position pos (lane l)
-__host__ __device__ inline long rec_idx(long pos, int l, int F, int f, int W) {
-  return (pos - l) * F + long(f) * W + l;
-}
-
-// record field counts (array widths, the same for every mode)
-template <int NS, int NT> struct Rec {
-  using D = Dims<NS, NT>;
-  static constexpr int NSOL = D::nsplit;                       // b, xs, x
-  static constexpr int NDINV = (D::nb * D::nb > 6 + NS * NS) ? D::nb * D::nb : 6 + NS * NS;
-  static constexpr int NSTATE = 6 + 2 * NS;                    // u v H eve pE pv | Y[NS] pr[NS] (split: prY at 6)
-  static constexpr int NFACE = 16;                             // mE mN mW mS (x,y) | cE cN cW cS | cCE cCN cCW cCS
+// step-block geometry of one part
+struct GroupMap {
+  int G, C, NSTEP, nstrip, Lw, FL, FC, RW;     // RW: record stride in elements
+  long nblk;
+  __host__ __device__ long lane(long blk, int f, int c, int k) const { return blk * RW + long(f) * Lw + k * C + c; }
+  __host__ __device__ long xs(long blk, int c, int k) const { return blk * RW + long(FL) * Lw + k * C + c; }
+  __host__ __device__ long drow(long blk, int q, int c, int k) const {
+    return blk * RW + long(FL + 1 + q) * Lw + k * C + c;
+  }
+  __host__ __device__ long cell(long blk, int f, int c) const {
+    return blk * RW + long(FL + 1 + G) * Lw + long(f) * C + c;
+  }
+  __host__ __device__ long res(long blk, int c, int k) const { return blk * Lw + k * C + c; }
 };
+__host__ __device__ inline GroupMap group_map(int ni, int nj, PartShape p, int C, int esz) {
+  GroupMap m;
+  m.G = p.G;
+  m.C = C;
+  m.FL = p.FL;
+  m.FC = p.FC;
+  m.NSTEP = nj + C - 1;
+  m.nstrip = (ni + C - 1) / C;
+  m.Lw = C * p.G;
+  m.RW = group_kib(p, esz) * 1024 / esz;
+  m.nblk = long(m.nstrip) * m.NSTEP;
+  return m;
+}
+// block and column of cell (i, j)
+__host__ __device__ inline long group_blk(const GroupMap &m, int i, int j, int &c) {
+  const int s = i / m.C;
+  c = i - s * m.C;
+  return long(s) * m.NSTEP + j + c;
+}
 
 // ----------------------------------------------------------- cell kernel
 // Residual R = sum_f F_f S_f - V S(Q), local time step, norms partials,
@@ -429,10 +467,11 @@ struct CellOut {
   double *R, *dtau, *part;     // part: per-block norm partials [2][nblocks]
   void *Dinv;                  // coupled: nb*nb fields; split: DF 6 fields then DC ns*ns fields
   void *b;                     // RHS, nsol fields
-  void *state, *face;          // strip layout only: JVP state and face coefficients
+  void *gR[2];                 // group schedule records of part 0 (coupled / flow) and 1 (species)
   double *src;                 // optional source vector [nv][N] (debug)
   int *bad;
-  int strip_w;                 // 0: cell-major layout (stride N); W > 0: strip layout of width W
+  int group_c;                 // 0: hyperplane schedule (cell-major records); > 0: group schedule
+  int group_cp[2];             // cells per wave of each part (group schedule)
   const float *Jsur;           // surrogate J_C [ns * ns][N] (flags bit 4)
   unsigned long long *ddfail;  // count of cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off (stall), use the exact block
@@ -518,18 +557,35 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     Prim<NS, NT> P;
     prim_from_q<NS, NT>(m, q, P);
     double Vdt = Vp / dt;
+    // hyperplane schedule: cell-major records (field f at f N + p)
+    const bool grp = out.group_c > 0;
     RT *bb = reinterpret_cast<RT *>(out.b);
-    // record element index: cell-major (field f at f N + p) or step-blocked strip layout
-    const int SWD = out.strip_w;
-    long spos = 0;
-    int sl = 0;
-    if (SWD > 0) {
-      const int sidx = i / SWD, NSTEP = g.nj + SWD - 1;
-      sl = i - sidx * SWD;
-      spos = (long(sidx) * NSTEP + j + sl) * SWD + sl;
-    }
-    auto IX = [&](int F, int f) -> long { return SWD > 0 ? (spos - sl) * F + long(f) * SWD + sl : long(f) * g.N + p; };
-    using Rc = Rec<NS, NT>;
+    RT *Dcm = reinterpret_cast<RT *>(out.Dinv);
+    // group schedule: E face = i-face (i+1, j), N face = j-face (i, j+1): outward
+    // normals of the receiving neighbours are -n; W face (i, j), S face (i, j): +n
+    const double SEh = 0.5 * SE, SNh = 0.5 * SN, SWh = 0.5 * SW, SSh = 0.5 * SS;
+    // push fields of a part: normals, then radius coefficient c = S/2 lam + S lam_v
+    auto write_cells = [&](int q, int part, int rv_lam, int rv_vis, const double *w) {
+      RT *Cf = reinterpret_cast<RT *>(out.gR[q]);
+      const GroupMap gm = group_map(g.ni, g.nj, part_shape(part, NS, NT), out.group_cp[q], sizeof(RT));
+      int cc;
+      const long blk = group_blk(gm, i, j, cc);
+      double f[14];
+      f[0] = P.u;
+      f[1] = P.v;
+      f[2] = -SEh * g.fi_nx[fE]; f[3] = -SEh * g.fi_ny[fE];
+      f[4] = SEh * Ri[size_t(rv_lam) * nfi + fE] + SE * Ri[size_t(rv_vis) * nfi + fE];
+      f[5] = -SNh * g.fj_nx[fN]; f[6] = -SNh * g.fj_ny[fN];
+      f[7] = SNh * Rj[size_t(rv_lam) * nfj + fN] + SN * Rj[size_t(rv_vis) * nfj + fN];
+      f[8] = SWh * g.fi_nx[fW]; f[9] = SWh * g.fi_ny[fW];
+      f[10] = SWh * Ri[size_t(rv_lam) * nfi + fW] + SW * Ri[size_t(rv_vis) * nfi + fW];
+      f[11] = SSh * g.fj_nx[fS]; f[12] = SSh * g.fj_ny[fS];
+      f[13] = SSh * Rj[size_t(rv_lam) * nfj + fS] + SS * Rj[size_t(rv_vis) * nfj + fS];
+#pragma unroll
+      for (int k = 0; k < 14; ++k) Cf[gm.cell(blk, k, cc)] = RT(f[k]);
+      if (w)
+        for (int k = 0; k < gm.G; ++k) Cf[gm.cell(blk, CF_W + k, cc)] = RT(w[k]);
+    };
     if (mode == 0) {
       // coupled: dS_z/dz, z = (rho, m_x, m_y, rhoE, [rhoe_ve], rho_0..rho_{ns-2})
       // storage derivative of omega_s: dw/dq_j = dw_dr + dw_dT dT/dq_j + dw_dTv dTv/dq_j
@@ -546,26 +602,53 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
       double Ai[NB][NB];
       bool ok = invert<NB>(A, Ai);
       if (!ok && out.bad) atomicMin(out.bad, p);
-      RT *Di = reinterpret_cast<RT *>(out.Dinv);
-#pragma unroll
-      for (int r = 0; r < NB; ++r)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) Di[IX(Rc::NDINV, r * NB + c)] = RT(Ai[r][c]);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
-      bb[IX(Rc::NSOL, 0)] = RT(-rsum);
-      bb[IX(Rc::NSOL, 1)] = RT(-R[NS]);
-      bb[IX(Rc::NSOL, 2)] = RT(-R[NS + 1]);
-      bb[IX(Rc::NSOL, 3)] = RT(-R[NS + 2]);
-      if (NT == 2) bb[IX(Rc::NSOL, 4)] = RT(-R[NS + 3]);
+      double bz[NB];
+      bz[0] = -rsum;
+      bz[1] = -R[NS];
+      bz[2] = -R[NS + 1];
+      bz[3] = -R[NS + 2];
+      if (NT == 2) bz[4] = -R[NS + 3];
 #pragma unroll
-      for (int s = 0; s < NS - 1; ++s) bb[IX(Rc::NSOL, NF + s)] = RT(-R[s]);
+      for (int s = 0; s < NS - 1; ++s) bz[NF + s] = -R[s];
+      if (!grp) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          bb[long(r) * g.N + p] = RT(bz[r]);
+#pragma unroll
+          for (int c = 0; c < NB; ++c) Dcm[long(r * NB + c) * g.N + p] = RT(Ai[r][c]);
+        }
+      } else {
+        const GroupMap gm = group_map(g.ni, g.nj, part_shape(PART_COUPLED, NS, NT), out.group_cp[0], sizeof(RT));
+        int cc;
+        const long blk = group_blk(gm, i, j, cc);
+        RT *L = reinterpret_cast<RT *>(out.gR[0]);
+        // coefficient of a = dmn - un x_0 in each JVP component, and the dp weights
+        double ca[NB], w[NB];
+        ca[0] = 0.0; ca[1] = P.u; ca[2] = P.v; ca[3] = P.H;
+        if (NT == 2) ca[4] = P.eve;
+        w[0] = P.pr[NS - 1]; w[1] = -P.pE * P.u; w[2] = -P.pE * P.v; w[3] = P.pE;
+        if (NT == 2) w[4] = P.pv;
+#pragma unroll
+        for (int s = 0; s < NS - 1; ++s) {
+          ca[NF + s] = P.Y[s];
+          w[NF + s] = P.pr[s] - P.pr[NS - 1];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          L[gm.lane(blk, 0, cc, r)] = RT(bz[r]);
+          L[gm.lane(blk, 1, cc, r)] = RT(ca[r]);
+#pragma unroll
+          for (int c = 0; c < NB; ++c) L[gm.drow(blk, c, cc, r)] = RT(Ai[r][c]);
+        }
+        write_cells(0, PART_COUPLED, R_LAM, R_LVK, w);
+      }
     } else {
       double dF = Vdt + 0.5 * slam + svF;
       double dC = Vdt + 0.5 * sU + svC;
-      RT *DF = reinterpret_cast<RT *>(out.Dinv);
-            // flow block: scalar rows, plus the rho e_ve row -V d omega_ve/dQ_F (frozen Y)
+      // flow block: scalar rows, plus the rho e_ve row -V d omega_ve/dQ_F (frozen Y)
       double df6[6];
       df6[0] = 1.0 / dF;
       for (int k = 1; k < 6; ++k) df6[k] = 0.0;
@@ -578,8 +661,6 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         if (piv == 0.0 && out.bad) atomicMin(out.bad, p);
         df6[5] = 1.0 / piv;
       }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) DF[IX(Rc::NDINV, k)] = RT(df6[k]);
       double A[NS][NS], Ai[NS][NS];
       bool use_sur = false, ok = false;
       if (try_sur) {
@@ -613,63 +694,73 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         ok = invert<NS>(A, Ai);
       }
       if (!ok && out.bad) atomicMin(out.bad, p);
-#pragma unroll
-      for (int r = 0; r < NS; ++r)
-#pragma unroll
-        for (int c = 0; c < NS; ++c) DF[IX(Rc::NDINV, 6 + r * NS + c)] = RT(Ai[r][c]);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
-      bb[IX(Rc::NSOL, 0)] = RT(-rsum);
-      bb[IX(Rc::NSOL, 1)] = RT(-R[NS]);
-      bb[IX(Rc::NSOL, 2)] = RT(-R[NS + 1]);
-      bb[IX(Rc::NSOL, 3)] = RT(-R[NS + 2]);
-      if (NT == 2) bb[IX(Rc::NSOL, 4)] = RT(-R[NS + 3]);
+      double bf[NF];
+      bf[0] = -rsum;
+      bf[1] = -R[NS];
+      bf[2] = -R[NS + 1];
+      bf[3] = -R[NS + 2];
+      if (NT == 2) bf[4] = -R[NS + 3];
+      if (!grp) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) bb[IX(Rc::NSOL, NF + s)] = RT(-R[s]);
-    }
-    if (out.strip_w > 0) {
-      // JVP state of this cell and the coefficients of its four pushes
-      RT *st = reinterpret_cast<RT *>(out.state);
-      RT *fc = reinterpret_cast<RT *>(out.face);
-      st[IX(Rc::NSTATE, 0)] = RT(P.u);
-      st[IX(Rc::NSTATE, 1)] = RT(P.v);
-      st[IX(Rc::NSTATE, 2)] = RT(P.H);
-      st[IX(Rc::NSTATE, 3)] = RT(P.eve);
-      st[IX(Rc::NSTATE, 4)] = RT(P.pE);
-      st[IX(Rc::NSTATE, 5)] = RT(P.pv);
-      if (mode == 0) {
+        for (int k = 0; k < 6; ++k) Dcm[long(k) * g.N + p] = RT(df6[k]);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          st[IX(Rc::NSTATE, 6 + s)] = RT(P.Y[s]);
-          st[IX(Rc::NSTATE, 6 + NS + s)] = RT(P.pr[s]);
-        }
+        for (int r = 0; r < NS; ++r)
+#pragma unroll
+          for (int c = 0; c < NS; ++c) Dcm[long(6 + r * NS + c) * g.N + p] = RT(Ai[r][c]);
+#pragma unroll
+        for (int k = 0; k < NF; ++k) bb[long(k) * g.N + p] = RT(bf[k]);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bb[long(NF + s) * g.N + p] = RT(-R[s]);
       } else {
-        double prY = 0.0;
+        // flow part: its inverse written as a dense nf x nf block
+        {
+          const GroupMap gm = group_map(g.ni, g.nj, part_shape(PART_FLOW, NS, NT), out.group_cp[0], sizeof(RT));
+          int cc;
+          const long blk = group_blk(gm, i, j, cc);
+          RT *L = reinterpret_cast<RT *>(out.gR[0]);
+          double prY = 0.0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) prY += P.pr[s] * P.Y[s];
-        st[IX(Rc::NSTATE, 6)] = RT(prY);
+          for (int s = 0; s < NS; ++s) prY += P.pr[s] * P.Y[s];
+          double ca[NF], w[NF], Df[NF][NF];
+          ca[0] = 0.0; ca[1] = P.u; ca[2] = P.v; ca[3] = P.H;
+          w[0] = prY; w[1] = -P.pE * P.u; w[2] = -P.pE * P.v; w[3] = P.pE;
+#pragma unroll
+          for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int c = 0; c < NF; ++c) Df[r][c] = (r == c && r < 4) ? df6[0] : 0.0;
+          if (NT == 2) {
+            ca[4] = P.eve;
+            w[4] = P.pv;
+            for (int c = 0; c < 4; ++c) Df[4][c] = df6[1 + c] * df6[0] * df6[5];
+            Df[4][4] = df6[5];
+          }
+#pragma unroll
+          for (int r = 0; r < NF; ++r) {
+            L[gm.lane(blk, 0, cc, r)] = RT(bf[r]);
+            L[gm.lane(blk, 1, cc, r)] = RT(ca[r]);
+#pragma unroll
+            for (int c = 0; c < NF; ++c) L[gm.drow(blk, c, cc, r)] = RT(Df[r][c]);
+          }
+          write_cells(0, PART_FLOW, R_LAM, R_LVF, w);
+        }
+        // species part
+        {
+          const GroupMap gm = group_map(g.ni, g.nj, part_shape(PART_SPECIES, NS, NT), out.group_cp[1], sizeof(RT));
+          int cc;
+          const long blk = group_blk(gm, i, j, cc);
+          RT *L = reinterpret_cast<RT *>(out.gR[1]);
+#pragma unroll
+          for (int r = 0; r < NS; ++r) {
+            L[gm.lane(blk, 0, cc, r)] = RT(-R[r]);
+#pragma unroll
+            for (int c = 0; c < NS; ++c) L[gm.drow(blk, c, cc, r)] = RT(Ai[r][c]);
+          }
+          write_cells(1, PART_SPECIES, R_UABS, R_LVC, nullptr);
+        }
       }
-      const int rv = mode == 0 ? R_LVK : R_LVF;
-      // E face = i-face (i+1, j), N face = j-face (i, j+1): outward normals of the
-      // receiving neighbours are -n; W face = i-face (i, j), S face = j-face (i, j): +n
-      const double SEh = 0.5 * SE, SNh = 0.5 * SN, SWh = 0.5 * SW, SSh = 0.5 * SS;
-      fc[IX(Rc::NFACE, 0)] = RT(-SEh * g.fi_nx[fE]);
-      fc[IX(Rc::NFACE, 1)] = RT(-SEh * g.fi_ny[fE]);
-      fc[IX(Rc::NFACE, 2)] = RT(-SNh * g.fj_nx[fN]);
-      fc[IX(Rc::NFACE, 3)] = RT(-SNh * g.fj_ny[fN]);
-      fc[IX(Rc::NFACE, 4)] = RT(SWh * g.fi_nx[fW]);
-      fc[IX(Rc::NFACE, 5)] = RT(SWh * g.fi_ny[fW]);
-      fc[IX(Rc::NFACE, 6)] = RT(SSh * g.fj_nx[fS]);
-      fc[IX(Rc::NFACE, 7)] = RT(SSh * g.fj_ny[fS]);
-      fc[IX(Rc::NFACE, 8)] = RT(SEh * Ri[size_t(R_LAM) * nfi + fE] + SE * Ri[size_t(rv) * nfi + fE]);
-      fc[IX(Rc::NFACE, 9)] = RT(SNh * Rj[size_t(R_LAM) * nfj + fN] + SN * Rj[size_t(rv) * nfj + fN]);
-      fc[IX(Rc::NFACE, 10)] = RT(SWh * Ri[size_t(R_LAM) * nfi + fW] + SW * Ri[size_t(rv) * nfi + fW]);
-      fc[IX(Rc::NFACE, 11)] = RT(SSh * Rj[size_t(R_LAM) * nfj + fS] + SS * Rj[size_t(rv) * nfj + fS]);
-      fc[IX(Rc::NFACE, 12)] = RT(SEh * Ri[size_t(R_UABS) * nfi + fE] + SE * Ri[size_t(R_LVC) * nfi + fE]);
-      fc[IX(Rc::NFACE, 13)] = RT(SNh * Rj[size_t(R_UABS) * nfj + fN] + SN * Rj[size_t(R_LVC) * nfj + fN]);
-      fc[IX(Rc::NFACE, 14)] = RT(SWh * Ri[size_t(R_UABS) * nfi + fW] + SW * Ri[size_t(R_LVC) * nfi + fW]);
-      fc[IX(Rc::NFACE, 15)] = RT(SSh * Rj[size_t(R_UABS) * nfj + fS] + SS * Rj[size_t(R_LVC) * nfj + fS]);
     }
     }
   }

@@ -2,7 +2,7 @@
 // count and the temperature model; instantiated per species count in
 // csi_inst.hip and dispatched through the IRunner interface.
 #pragma once
-#include "csi_strip.hpp"
+#include "csi_group.hpp"
 #include "csi_surrogate.hpp"
 
 namespace csi {
@@ -12,13 +12,12 @@ struct WS {
   Mech *mech;
   double *V, *xc, *yc, *xn, *yn, *fi_nx, *fi_ny, *fi_S, *fj_nx, *fj_ny, *fj_S;
   double *qfs, *Q, *prim, *Fi, *Fj, *Ri, *Rj, *R, *dtau, *src, *qw, *part, *norms, *r0, *hist;
-  void *b, *dqs, *dq, *Dinv;
-  void *state, *face, *bnd;  // strip-layout sweep records and strip-boundary pushes
-  int *sync;                 // [nstrip] fwd progress, [nstrip] bwd progress, [2] tickets
+  void *b, *dqs, *dq, *Dinv;  // hyperplane schedule: cell-major records and results
+  GroupBufs grp[2];           // group schedule: part 0 (coupled / flow), part 1 (species)
+  long long *trace;           // optional per-strip sweep trace [fwd, bwd][part][ni][TR_N] (null: off)
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
-  int strip_w;               // 0: one launch per hyperplane; 16 or 64: persistent strip kernels
-  int pub_every;             // strip progress published every this many steps
+  int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels
   long spin_limit;
   SurArgs sur;               // surrogate network (packed operands, biases, scales) and its J_C buffer
 };
@@ -53,6 +52,13 @@ IRunner *make_runner(int ns, int nt);
 
 inline int nblocks(long n, int b = 256) { return int((n + b - 1) / b); }
 
+// cells per wave of part q (0: coupled / flow, 1: species) under the group
+// schedule (group_c > 0): 64 / G, the widest strip of G-lane groups
+template <int NS, int NT> inline int group_cells(int group_c, int mode, int q) {
+  const int G = part_shape(q == 1 ? PART_SPECIES : mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT).G;
+  return group_c > 0 ? 64 / G : 0;
+}
+
 template <int NS, int NT> class Runner : public IRunner {
  public:
   int nprim() const override { return PF<NS>::N; }
@@ -74,7 +80,9 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                   bool stoppable) override {
-    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, w.state, w.face, w.src, w.flags + FL_SING, w.strip_w,
+    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].R, w.grp[1].R},
+              w.src, w.flags + FL_SING, w.group_c,
+              {group_cells<NS, NT>(w.group_c, mode, 0), group_cells<NS, NT>(w.group_c, mode, 1)},
               w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
@@ -106,32 +114,59 @@ template <int NS, int NT> class Runner : public IRunner {
     return hipGetLastError();
   }
 
+  template <typename RT, int MODE>
+  static void launch_pair(const Geo &g, const GroupArgs &a, dim3 gr, dim3 bl, hipStream_t st, const int *done,
+                          hipEvent_t mid) {
+    constexpr size_t lds = group_lds_bytes<NS, NT, RT, MODE>();
+    static_assert(lds + sizeof(GroupSync) <= 160 * 1024, "sweep ring exceeds the LDS");
+    static bool attr = false;  // dynamic LDS above 64 KiB must be allowed per kernel
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_group_sweep<NS, NT, RT, MODE, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_group_sweep<NS, NT, RT, MODE, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_group_sweep<NS, NT, RT, MODE, true>), gr, bl, lds, st, g, a, done);
+    if (mid) (void)hipEventRecord(mid, st);
+    GroupArgs ab = a;
+    if (ab.trace) ab.trace += 2L * g.ni * TR_N;
+    hipLaunchKernelGGL((k_group_sweep<NS, NT, RT, MODE, false>), gr, bl, lds, st, g, ab, done);
+  }
+
   // mid (optional) is recorded between the forward and the backward sweep
   template <typename RT>
   hipError_t sweeps_t(const Geo &g, const WS &w, hipStream_t st, int mode, bool stoppable, hipEvent_t mid) {
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
-    if (w.strip_w > 0) {
-      StripMap sm = strip_map(g.ni, g.nj, w.strip_w);
-      StripArgs a{w.b, w.Dinv, w.state, w.face, w.dqs, w.dq, w.bnd, w.sync, w.flags + FL_ABORT, w.pub_every,
-                  w.spin_limit};
-      hipLaunchKernelGGL(k_zero_ints<NS>, dim3(1), dim3(64), 0, st, w.sync, strip_sync_ints(sm.nstrip), done);
-      // split: one wavefront per strip for each of the two independent parts
-      const dim3 gr(sm.nstrip, mode == 0 ? 1 : 2), bl(64);
-      if (w.strip_w == 16 || NS > 11) {  // 64-column strips are compiled for ns <= 11 only
-        if (mode == 0) hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
-        else hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
-        if (mid) (void)hipEventRecord(mid, st);
-        if (mode == 0) hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 0>), gr, bl, 0, st, g, a, done);
-        else hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 16, 1>), gr, bl, 0, st, g, a, done);
-      } else {
-        if constexpr (NS <= 11) {
-          if (mode == 0) hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
-          else hipLaunchKernelGGL((k_strip_fwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
-          if (mid) (void)hipEventRecord(mid, st);
-          if (mode == 0) hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 0>), gr, bl, 0, st, g, a, done);
-          else hipLaunchKernelGGL((k_strip_bwd<NS, NT, RT, 64, 1>), gr, bl, 0, st, g, a, done);
+    if (w.group_c > 0) {
+      GroupArgs a{};
+      a.abort_flag = w.flags + FL_ABORT;
+      a.spin_limit = w.spin_limit;
+      a.trace = w.trace;
+      const int nparts = mode == 0 ? 1 : 2;
+      int nstrip = 0;
+      long maxw = 0;
+      GroupReset rs{};
+      for (int q = 0; q < nparts; ++q) {
+        const int C = group_cells<NS, NT>(w.group_c, mode, q);
+        a.part[q] = GroupPart{w.grp[q], C};
+        const PartShape ps = part_shape(q == 1 ? PART_SPECIES : mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT);
+        const GroupMap m = group_map(g.ni, g.nj, ps, C, sizeof(RT));
+        nstrip = m.nstrip > nstrip ? m.nstrip : nstrip;
+        const long words = long(m.nstrip) * g.nj * ps.G * long(sizeof(RT)) / 4;
+        maxw = words > maxw ? words : maxw;
+        rs.tickets[q] = w.grp[q].tickets;
+        for (int f = 0; f < 2; ++f) {
+          rs.bnd[2 * q + f] = reinterpret_cast<unsigned *>(w.grp[q].bnd[f]);
+          rs.nw[2 * q + f] = words;
         }
       }
+      const int rb = nblocks(maxw) < 1024 ? (nblocks(maxw) > 0 ? nblocks(maxw) : 1) : 1024;
+      hipLaunchKernelGGL(k_group_reset<NS>, dim3(rb), dim3(256), 0, st, rs, done);
+      // split: one workgroup per strip for each of the two independent parts
+      const dim3 gr(nstrip, nparts), bl(192);
+      if (mode == 0) launch_pair<RT, 0>(g, a, gr, bl, st, done, mid);
+      else launch_pair<RT, 1>(g, a, gr, bl, st, done, mid);
       return hipGetLastError();
     }
     SweepArgs a{w.prim, w.Ri, w.Rj, w.Dinv, w.b, w.dqs, w.dq, mode};
@@ -157,12 +192,17 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind, bool stoppable) override {
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    IncView iv{{w.grp[0].x, w.grp[1].x}, {0, 0}};
+    if (w.group_c > 0) {
+      iv.C[0] = group_cells<NS, NT>(w.group_c, mode, 0);
+      iv.C[1] = group_cells<NS, NT>(w.group_c, mode, 1);
+    }
     if (prec == 0)
       hipLaunchKernelGGL((k_update<NS, NT, double>), dim3(nblocks(g.N)), dim3(256), 0, st, g, w.mech, w.Q, w.dq, mode, kind,
-                         w.flags + FL_CLIP, w.flags + FL_BAD, done, w.strip_w);
+                         w.flags + FL_CLIP, w.flags + FL_BAD, done, iv);
     else
       hipLaunchKernelGGL((k_update<NS, NT, float>), dim3(nblocks(g.N)), dim3(256), 0, st, g, w.mech, w.Q, w.dq, mode, kind,
-                         w.flags + FL_CLIP, w.flags + FL_BAD, done, w.strip_w);
+                         w.flags + FL_CLIP, w.flags + FL_BAD, done, iv);
     return hipGetLastError();
   }
 

@@ -217,6 +217,14 @@ __global__ void __launch_bounds__(256) k_sweep_bwd_hp(Geo g, SweepArgs a, int k,
 }
 
 // ------------------------------------------------------------ corrections
+// where k_update finds the increment dQ: C[0] == 0: cell-major array; else
+// the group-schedule results of part 0 (coupled / flow, C[0] cells per wave)
+// and part 1 (species, C[1])
+struct IncView {
+  const void *x[2];
+  int C[2];
+};
+
 // coupled closure rho_ns = rho - sum_{s<ns} rho_s; split CC1 (increment
 // normalisation with W_s = rho_s/rho) or CC2 (mass-fraction normalisation),
 // paper Section 2.3 "Consistence correction"; negative partial densities are
@@ -225,28 +233,39 @@ template <int NS, int NT, typename RT>
 __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ mech, double *__restrict__ Q,
                                                 const void *__restrict__ dqv, int mode,
                                                 int kind, int *__restrict__ nclip, int *__restrict__ bad,
-                                                const int *__restrict__ done, int strip_w) {
+                                                const int *__restrict__ done, IncView iv) {
   using D = Dims<NS, NT>;
   constexpr int NF = D::nf;
   if (done && *done) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.N) return;
   const RT *dq = reinterpret_cast<const RT *>(dqv);
-  // component k of the increment: cell-major, or step-blocked strip layout
-  long spos = 0;
-  int sl = 0;
-  if (strip_w > 0) {
-    const int i = p % g.ni, j = p / g.ni, sidx = i / strip_w, NSTEP = g.nj + strip_w - 1;
-    sl = i - sidx * strip_w;
-    spos = (long(sidx) * NSTEP + j + sl) * strip_w + sl;
+  // component k of the increment: cell-major (hyperplane schedule), or the
+  // step-blocked results of the group schedule (part 0: the first G0
+  // unknowns; part 1: the species of the split form)
+  const int i = p % g.ni, j = p / g.ni;
+  const int G0 = mode == 0 ? D::nb : NF;
+  GroupMap m0{}, m1{};
+  long b0 = 0, b1 = 0;
+  int c0 = 0, c1 = 0;
+  if (iv.C[0] > 0) {
+    m0 = group_map(g.ni, g.nj, part_shape(mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT), iv.C[0], sizeof(RT));
+    b0 = group_blk(m0, i, j, c0);
+    if (mode != 0) {
+      m1 = group_map(g.ni, g.nj, part_shape(PART_SPECIES, NS, NT), iv.C[1], sizeof(RT));
+      b1 = group_blk(m1, i, j, c1);
+    }
   }
-  auto IX = [&](int k) -> long {
-    return strip_w > 0 ? (spos - sl) * Rec<NS, NT>::NSOL + long(k) * strip_w + sl : long(k) * g.N + p;
+  const RT *x0 = reinterpret_cast<const RT *>(iv.x[0]), *x1 = reinterpret_cast<const RT *>(iv.x[1]);
+  auto IX = [&](int k) -> RT {
+    if (iv.C[0] == 0) return dq[long(k) * g.N + p];
+    if (k < G0) return x0[m0.res(b0, c0, k)];
+    return x1[m1.res(b1, c1, k - G0)];
   };
   double rs[NS], rho = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) { rs[s] = Q[size_t(s) * g.N + p]; rho += rs[s]; }
-  double drho = double(dq[IX(0)]);
+  double drho = double(IX(0));
   double target = rho + drho;
   double nr[NS];
   bool clip = false;
@@ -254,7 +273,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
     double sum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s) {
-      double d = double(dq[IX(NF + s)]);
+      double d = double(IX(NF + s));
       nr[s] = rs[s] + d;
       sum += d;
     }
@@ -262,14 +281,14 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   } else if (kind == 1) {
     double sum = 0.0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sum += double(dq[IX(NF + s)]);
+    for (int s = 0; s < NS; ++s) sum += double(IX(NF + s));
 #pragma unroll
-    for (int s = 0; s < NS; ++s) nr[s] = rs[s] + double(dq[IX(NF + s)]) + (rs[s] / rho) * (drho - sum);
+    for (int s = 0; s < NS; ++s) nr[s] = rs[s] + double(IX(NF + s)) + (rs[s] / rho) * (drho - sum);
   } else {
     double t[NS], sum = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      double v = rs[s] + double(dq[IX(NF + s)]);
+      double v = rs[s] + double(IX(NF + s));
       if (v < 0.0) clip = true;
       t[s] = v > 0.0 ? v : 0.0;
       sum += t[s];
@@ -293,12 +312,12 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   if (!(target > 0.0) && bad) atomicMin(bad, p);
 #pragma unroll
   for (int s = 0; s < NS; ++s) Q[size_t(s) * g.N + p] = nr[s];
-  Q[size_t(NS) * g.N + p] += double(dq[IX(1)]);
-  Q[size_t(NS + 1) * g.N + p] += double(dq[IX(2)]);
-  Q[size_t(NS + 2) * g.N + p] += double(dq[IX(3)]);
+  Q[size_t(NS) * g.N + p] += double(IX(1));
+  Q[size_t(NS + 1) * g.N + p] += double(IX(2));
+  Q[size_t(NS + 2) * g.N + p] += double(IX(3));
   if (NT == 2) {
     // positivity of the vibrational-electronic energy: floor at Tv = TV_FLOOR
-    double eve = Q[size_t(NS + 3) * g.N + p] + double(dq[IX(4)]), fl = 0.0;
+    double eve = Q[size_t(NS + 3) * g.N + p] + double(IX(4)), fl = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) fl += nr[s] * eve_s(*mech, s, TV_FLOOR);
     if (eve < fl) {

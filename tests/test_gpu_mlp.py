@@ -281,7 +281,7 @@ def test_surrogate_dominance_selection(name):
         s.set_state(q0)
         s.residual(10.0)
         s.implicit_op(csi.SPLIT, csi.FP64, jac)
-        res[jac] = s.get("Dinv", csi.SPLIT)[6:].T.reshape(N, ns, ns)
+        res[jac] = s.get("Dinv", csi.SPLIT)[m.nf * m.nf:].T.reshape(N, ns, ns)
     acc_g = np.any(res[csi.JAC_SURROGATE] != res[csi.JAC_EXACT], axis=(1, 2))
     o.set_state(q0)
     o.residual(10.0)
