@@ -162,32 +162,39 @@ template <int NS, int NT, int P> struct GLayout {
   static constexpr int OX = FL * Lw, OD = OX + Lw, OC = OD + G * Lw;  // dQ*, D^-1 rows, cell fields
 };
 
-// per-step record of one lane
+// per-step record of one lane.  The forward sweep pushes through faces E, N,
+// the backward sweep through W, S.
 template <int NS, int NT, typename RT, int P, bool FWD> struct GRec {
   using Gp = GPart<NS, NT, P>;
   using Ly = GLayout<NS, NT, P>;
-  static constexpr int G = Gp::G;
-  RT b;        // forward: RHS b_k; backward: dQ*_k
-  RT ca;       // JVP parts: coefficient of a in component k
-  RT Dr[G];    // row k of D^-1
-  RT u, v;     // cell velocity
-  RT f[6];     // push 1 (mx, my, c), push 2 (mx, my, c)
-  RT w[Gp::JVP ? G : 1];  // dp weights (JVP parts)
+  static constexpr int G = Gp::G, F0 = FWD ? 0 : 2;
+  RT b;          // forward: RHS b_k; backward: dQ*_k
+  RT Dr[G];      // row k of D^-1
+  // JVP parts: coefficient of a, and per push face: g_k, cp_k, (m_x, m_y, u.m), dp weights
+  RT ca, gk[2], cp[2], mx[2], my[2], un[2];
+  RT w[Gp::JVP ? G : 1];
+  RT coef[2];    // species part: u.m - c per push face
 
   // from one step block in LDS: L = block + k C + c (lane fields), Q = block + OC + c (cell fields)
   __device__ __forceinline__ void load(const RT *L, const RT *Q) {
     b = FWD ? L[0] : L[Ly::OX];
-    if (Gp::JVP) ca = L[Ly::Lw];
 #pragma unroll
     for (int q = 0; q < G; ++q) Dr[q] = L[Ly::OD + q * Ly::Lw];
-    u = Q[CF_U * Ly::C];
-    v = Q[CF_V * Ly::C];
-    constexpr int p0 = CF_PUSH + (FWD ? 0 : 6);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] = Q[(p0 + q) * Ly::C];
     if (Gp::JVP) {
+      ca = L[LF_CA * Ly::Lw];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        gk[f] = L[(LF_FACE + 2 * (F0 + f)) * Ly::Lw];
+        cp[f] = L[(LF_FACE + 2 * (F0 + f) + 1) * Ly::Lw];
+        mx[f] = Q[3 * (F0 + f) * Ly::C];
+        my[f] = Q[(3 * (F0 + f) + 1) * Ly::C];
+        un[f] = Q[(3 * (F0 + f) + 2) * Ly::C];
+      }
 #pragma unroll
       for (int q = 0; q < G; ++q) w[q] = Q[(CF_W + q) * Ly::C];
+    } else {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) coef[f] = Q[(F0 + f) * Ly::C];
     }
   }
 };
@@ -216,25 +223,22 @@ template <bool UP> __device__ __forceinline__ double lane_move(double v) {
   return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
 }
 
-// component k of the push O x for one face (m = half-length-scaled normal of
-// the receiving cell, c = radius coefficient): JVP parts
-//   o_k = un x'_k + ca_k a + cp_k dp + [k = 0] dmn - c x_k,
-//   un = u.m, dmn = x_1 m_x + x_2 m_y, a = dmn - un x_0, dp = w.x,
-//   x'_k = x_k (k > 0), cp = (0, m_x, m_y, un, 0, ...);
-// species part: (u.m - c) x_k.
+// component k of the push O x through push face f (JVP parts):
+//   o_k = ca_k a + [k = 0] dmn + g_k x_k + cp_k dp,
+//   dmn = x_1 m_x + x_2 m_y, a = dmn - (u.m) x_0, dp = w.x,
+// the spectral-split flux Jacobian-vector product 1/2 S (A(n) x - lam x) minus
+// the viscous radius term (m = S/2 n of the receiving cell); species part:
+// (u.m - c) x_k.
 template <int NS, int NT, typename RT, int P, bool FWD>
-__device__ __forceinline__ RT push_comp(const GRec<NS, NT, RT, P, FWD> &R, int q, int k, RT xk, const RT *xall,
+__device__ __forceinline__ RT push_comp(const GRec<NS, NT, RT, P, FWD> &R, int f, RT beta, RT xk, const RT *xall,
                                         RT dp) {
 #pragma clang fp contract(off)
-  const RT mx = R.f[3 * q], my = R.f[3 * q + 1], c = R.f[3 * q + 2];
-  const RT un = fmad(R.v, my, R.u * mx);
-  if (P == PART_SPECIES) return (un - c) * xk;
-  const RT dmn = fmad(xall[2], my, xall[1] * mx);
-  const RT a = fmad(-un, xall[0], dmn);
-  RT o = fmad(-c, xk, R.ca * a);
-  o = k == 0 ? o + dmn : fmad(un, xk, o);
-  const RT cp = k == 1 ? mx : k == 2 ? my : k == 3 ? un : RT(0);
-  return fmad(cp, dp, o);
+  if (P == PART_SPECIES) return R.coef[f] * xk;
+  const RT dmn = fmad(xall[2], R.my[f], xall[1] * R.mx[f]);
+  const RT a = fmad(-R.un[f], xall[0], dmn);
+  RT o = fmad(R.gk[f], xk, R.ca * a);
+  o = fmad(beta, dmn, o);
+  return fmad(R.cp[f], dp, o);
 }
 
 // ------------------------------------------------------------ the three waves
@@ -288,37 +292,6 @@ __device__ __forceinline__ long copy_wave(const char *R, long blk0, int dir, int
   return spins;
 }
 
-// wave 2: the G pushes that enter the strip at each step, from the
-// neighbouring strip (slot idx(e) < 0: no push at step e)
-template <typename RT, int G, int DEPTH, typename IDX>
-__device__ __forceinline__ long boundary_wave(const RT *bnd, IDX idx, bool any, int NSTEP, RT *bring, GroupSync &sy,
-                                              int *abort_flag, long spin_limit) {
-  const int lane = threadIdx.x & 63;
-  if (!any) {  // a strip at the edge of the grid takes no pushes
-    lds_set(&sy.bnd_ready, NSTEP);
-    return 0;
-  }
-  int slot = 0, seen = 0;
-  bool ok = true;
-  long spins = 0, slot_spins = 0;
-  for (int e = 0; e < NSTEP; ++e) {
-    const long at = idx(e);
-    if (at >= 0) {
-      if (e >= DEPTH && seen < e - DEPTH + 1) {
-        if (!lds_wait(&sy.consumed, e - DEPTH + 1, abort_flag, spin_limit, slot_spins, seen, 1)) return spins;
-      }
-      if (lane < G) {
-        RT v = RT(0);
-        if (ok) ok = take_push(bnd + at + lane, v, abort_flag, spin_limit, spins);
-        bring[slot * G + lane] = v;
-      }
-    }
-    if (++slot == DEPTH) slot = 0;
-    lds_set(&sy.bnd_ready, e + 1);
-  }
-  return spins;
-}
-
 // spin until *p >= need (rare path of the compute wave); returns the value
 // read, or sets the abort flag and clears live on timeout / abort
 __device__ __forceinline__ int lds_spin(const int *p, int need, int *abort_flag, long spin_limit, long &spins,
@@ -336,6 +309,62 @@ __device__ __forceinline__ int lds_spin(const int *p, int need, int *abort_flag,
   spins += n;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   return v;
+}
+
+// wave 2: the G pushes that enter the strip at each step, from the
+// neighbouring strip.  The steps that take a push form one run [e0, e1); the
+// push of step e sits at bnd[at0 + dir (e - e0) G + k].  The wave polls a
+// window of up to 64 / G consecutive steps with one load per lane and hands
+// over every leading step whose G components have all landed, so that it
+// keeps up with the neighbour however far behind it starts.
+template <typename RT, int G, int DEPTH>
+__device__ __forceinline__ long boundary_wave(const RT *bnd, long at0, int dir, int e0, int e1, int NSTEP, RT *bring,
+                                              GroupSync &sy, int *abort_flag, long spin_limit) {
+  using U = typename UBits<RT>::T;
+  constexpr int W = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int w = lane / G, k = lane - w * G;
+  if (e0 >= e1) {  // a strip at the edge of the grid takes no pushes
+    lds_set(&sy.bnd_ready, NSTEP);
+    return 0;
+  }
+  lds_set(&sy.bnd_ready, e0);
+  long spins = 0, n = 0;
+  int e = e0, seen = 0;
+  while (e < e1) {
+    // steps e .. e + nw - 1 fit the ring once the compute wave has read step e + nw - 1 - DEPTH
+    int free_slots = seen + DEPTH - e;
+    if (free_slots <= 0) {
+      long s2 = 0;
+      bool live = true;
+      seen = lds_spin(&sy.consumed, e - DEPTH + 1, abort_flag, spin_limit, s2, live);
+      if (!live) return spins;
+      free_slots = seen + DEPTH - e;
+    }
+    const int nw = min(W, min(free_slots, e1 - e));
+    U u = ~U(0);
+    if (w < nw)
+      u = __hip_atomic_load(reinterpret_cast<const U *>(bnd + at0 + long(dir) * (e - e0 + w) * G + k), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long got = __ballot(w < nw && u != ~U(0));
+    int cnt = 0;
+    constexpr unsigned long long gm = (1ull << G) - 1;
+    while (cnt < nw && ((got >> (cnt * G)) & gm) == gm) ++cnt;
+    if (cnt == 0) {
+      if (++n > spin_limit || ((n & 63) == 0 && aborted(abort_flag))) {
+        set_abort(abort_flag);
+        return spins;
+      }
+      ++spins;
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    if (w < cnt) bring[((e + w) % DEPTH) * G + k] = __builtin_bit_cast(RT, u);
+    e += cnt;
+    lds_set(&sy.bnd_ready, e);
+  }
+  lds_set(&sy.bnd_ready, NSTEP);
+  return spins;
 }
 
 // wave 0: the sweep recurrence.  Lane (c, k) = k C + c; the push of column c
@@ -369,8 +398,12 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
   // the column that takes a push from the neighbouring strip
   constexpr int edge = FWD ? 0 : C - 1;
   const bool has_nb = FWD ? s > 0 : s < m.nstrip - 1;
-  const bool h1 = FWD ? i > 0 : i + 1 < g.ni, s1 = FWD ? i + 1 < g.ni : i > 0;
-  const bool send_nb = c == C - 1 - edge && (FWD ? i + 1 < g.ni : s > 0);
+  // lanes that hand their push to the neighbouring strip (only real components)
+  const bool send_nb = lane_ok && c == C - 1 - edge && (FWD ? i + 1 < g.ni : s > 0);
+  // lanes whose in-strip push source is not a cell: the edge column, and in
+  // the backward sweep the last column of the grid (its east neighbour is padding)
+  const bool no_src = c == edge || (!FWD && i + 1 >= g.ni);
+  const RT beta = k == 0 ? RT(1) : RT(0);
   const int lofs = kk * C + c, cofs = Ly::OC + c;
   bool live = true;
   int rec_seen = lds_spin(&sy.rec_ready, 1, a.abort_flag, a.spin_limit, rsp, live);
@@ -388,16 +421,13 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
       const RT v = bring[slot * G + kk];
       in1 = c == edge ? v : in1;
     }
-    // r = b -/+ pushes, gathered over the group
+    // r = b -/+ pushes, gathered over the group.  in1 is zero at the edge
+    // column unless a neighbouring strip pushed; in2 comes from the previous
+    // cell of the column, which does not exist at its first cell.
     const bool h2 = FWD ? j > 0 : j + 1 < g.nj;
-    RT r = FWD ? cur.b : RT(0);
-    if (FWD) {
-      r = h1 ? r - in1 : r;
-      r = h2 ? r - in2 : r;
-    } else {
-      r = h1 ? r + in1 : r;
-      r = h2 ? r + in2 : r;
-    }
+    RT r = FWD ? cur.b - in1 : in1;
+    const RT t2 = h2 ? in2 : RT(0);
+    r = FWD ? r - t2 : r + t2;
     RT rg[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) rg[q] = gather(r, gaddr[q]);
@@ -414,7 +444,6 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
 #pragma unroll
     for (int q = 1; q < G; ++q) y = fmad(cur.Dr[q], rg[q], y);
     const RT x = FWD ? y : cur.b - y;
-    const bool s2 = FWD ? j + 1 < g.nj : j > 0;
     RT p1, p2;
     if (JVP) {
       RT xall[G];
@@ -424,20 +453,21 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
         xall[q] = gather(x, gaddr[q]);
         dp = q == 0 ? cur.w[0] * xall[0] : fmad(cur.w[q], xall[q], dp);
       }
-      p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, k, x, xall, dp);
-      p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, k, x, xall, dp);
+      p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, beta, x, xall, dp);
+      p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, beta, x, xall, dp);
     } else {
-      p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, k, x, nullptr, RT(0));
-      p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, k, x, nullptr, RT(0));
+      p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, beta, x, nullptr, RT(0));
+      p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, beta, x, nullptr, RT(0));
     }
-    const bool active = col_ok && j >= 0 && j < g.nj;
-    p1 = active && s1 ? p1 : RT(0);
-    p2 = active && s2 ? p2 : RT(0);
-    if (active) {
-      out[FWD ? (b0 + d) * SLOT + Ly::OX + k * C + c : (b0 + d) * Ly::Lw + k * C + c] = x;
-      if (send_nb) put_push(bnd + (long(FWD ? s : s - 1) * g.nj + j) * G + k, p1);
-    }
+    // The pushes of a cell outside the grid reach only cells outside the grid
+    // (the same j, or i beyond the last column), except the in-column push
+    // into the first cell of the column, which h2 excludes, and the backward
+    // push from beyond the last column, which no_src excludes; results
+    // outside the grid land in padding slots of the step blocks.
+    if (lane_ok) out[FWD ? (b0 + d) * SLOT + Ly::OX + k * C + c : (b0 + d) * Ly::Lw + k * C + c] = x;
+    if (send_nb && j >= 0 && j < g.nj) put_push(bnd + (long(FWD ? s : s - 1) * g.nj + j) * G + k, p1);
     in1 = lane_move<FWD>(p1);
+    in1 = no_src ? RT(0) : in1;
     in2 = p2;
   };
 #pragma unroll 1
@@ -477,20 +507,16 @@ __device__ __forceinline__ void group_part(const Geo &g, const GroupArgs &a, int
     const RT *bnd = reinterpret_cast<const RT *>(gp.b.bnd[FWD ? 0 : 1]);
     const int nj = g.nj, C = m.C, NSTEP = m.NSTEP, last = m.nstrip - 1;
     if (FWD) {
-      // west pushes of column 0: cell (i0, j = d), written by strip s - 1
-      const long sp = boundary_wave<RT, G, Pp::DEPTH>(
-          bnd, [=](int e) -> long { return s > 0 && e < nj ? (long(s - 1) * nj + e) * G : -1L; }, s > 0, NSTEP,
-          bring, sy, a.abort_flag, a.spin_limit);
+      // west pushes of column 0: cell (i0, j = d = e), written by strip s - 1
+      const long sp = boundary_wave<RT, G, Pp::DEPTH>(bnd, s > 0 ? long(s - 1) * nj * G : 0L, 1, 0, s > 0 ? nj : 0,
+                                                      NSTEP, bring, sy, a.abort_flag, a.spin_limit);
       if (tr && lane == 0) tr[TR_POLL] = sp;
     } else {
-      // east pushes of column C - 1: cell (i0 + C - 1, j = d - C + 1), written by strip s + 1
-      const long sp = boundary_wave<RT, G, Pp::DEPTH>(
-          bnd,
-          [=](int e) -> long {
-            const int jl = NSTEP - 1 - e - (C - 1);
-            return s < last && jl >= 0 && jl < nj ? (long(s) * nj + jl) * G : -1L;
-          },
-          s < last, NSTEP, bring, sy, a.abort_flag, a.spin_limit);
+      // east pushes of column C - 1: cell (i0 + C - 1, j = d - C + 1), d = NSTEP - 1 - e, written by strip
+      // s + 1; j runs from nj - 1 (e = 0) down to 0 (e = nj - 1)
+      const long sp = boundary_wave<RT, G, Pp::DEPTH>(bnd, s < last ? (long(s) * nj + nj - 1) * G : 0L, -1, 0,
+                                                      s < last ? nj : 0, NSTEP, bring, sy, a.abort_flag,
+                                                      a.spin_limit);
       if (tr && lane == 0) tr[TR_POLL] = sp;
     }
   } else {

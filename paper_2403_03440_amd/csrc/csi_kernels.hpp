@@ -387,10 +387,12 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
 // stored in step blocks blk = s NSTEP + d (strip s, step d = i - i0 + j,
 // NSTEP = nj + C - 1); one block is contiguous so that a sweep wave can copy
 // it to LDS with whole-KiB transfers:
-//   lane fields  [F_L][G C]   RHS b_k, coefficient of a in the JVP (lane (c, k) at k C + c)
+//   lane fields  [F_L][G C]   lane (c, k) at k C + c: RHS b_k; JVP parts also the
+//                             coefficients of the push (see the sweeps)
 //   dQ*          [G C]        written by the forward sweep for the backward sweep
 //   D^-1 rows    [G][G C]     (D^-1)_km at lane (c, k), field m
-//   cell fields  [F_C][C]     u, v, push normals and radii, dp weights
+//   cell fields  [F_C][C]     per face E, N, W, S: JVP parts the scaled normal and
+//                             u.m, then the dp weights; species part u.m - c
 // padded to a whole number of KiB (the size at C = 64 / G, so the stride does
 // not depend on C).  The backward results dQ are a separate array [blk][G C].
 // Lanes are component-major (k C + c), so that the push of column c reaches
@@ -398,7 +400,9 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
 
 // parts of the implicit operator swept by one wavefront
 enum { PART_COUPLED = 0, PART_FLOW = 2, PART_SPECIES = 3 };
-enum { CF_U = 0, CF_V = 1, CF_PUSH = 2, CF_W = 14 };
+// lane fields of the JVP parts: b, ca, then (g, cp) per face E, N, W, S;
+// cell fields: (m_x, m_y, u.m) per face, then the dp weights
+enum { LF_B = 0, LF_CA = 1, LF_FACE = 2, CF_W = 12 };
 
 // lanes per cell, lane fields, cell fields of a part
 struct PartShape {
@@ -406,8 +410,8 @@ struct PartShape {
 };
 __host__ __device__ constexpr PartShape part_shape(int part, int ns, int nt) {
   const int nf = nt == 2 ? 5 : 4, nb = nf + ns - 1;
-  return part == PART_COUPLED ? PartShape{nb, 2, 14 + nb} : part == PART_FLOW ? PartShape{nf, 2, 14 + nf}
-                                                                               : PartShape{ns, 1, 14};
+  return part == PART_COUPLED ? PartShape{nb, 10, CF_W + nb} : part == PART_FLOW ? PartShape{nf, 10, CF_W + nf}
+                                                                                 : PartShape{ns, 1, 4};
 }
 // KiB per step record (element size esz)
 __host__ __device__ constexpr int group_kib(PartShape p, int esz) {
@@ -565,26 +569,49 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     // normals of the receiving neighbours are -n; W face (i, j), S face (i, j): +n
     const double SEh = 0.5 * SE, SNh = 0.5 * SN, SWh = 0.5 * SW, SSh = 0.5 * SS;
     // push fields of a part: normals, then radius coefficient c = S/2 lam + S lam_v
-    auto write_cells = [&](int q, int part, int rv_lam, int rv_vis, const double *w) {
-      RT *Cf = reinterpret_cast<RT *>(out.gR[q]);
+    // push data of a part (q: record array): per face E, N, W, S the outward
+    // normal of the receiving cell scaled by S/2 (m), u.m and the radius
+    // coefficient c = S/2 lam + S lam_v.  JVP parts (w: dp weights, ca: the
+    // coefficient of a): cell fields (m_x, m_y, u.m) and per lane
+    //   g_k = [k > 0] u.m - c,  cp_k = (0, m_x, m_y, u.m, 0, ...)_k;
+    // species part: u.m - c per face.
+    auto write_push = [&](int q, int part, int rv_lam, int rv_vis, const double *w, const double *ca) {
+      RT *Rr = reinterpret_cast<RT *>(out.gR[q]);
       const GroupMap gm = group_map(g.ni, g.nj, part_shape(part, NS, NT), out.group_cp[q], sizeof(RT));
       int cc;
       const long blk = group_blk(gm, i, j, cc);
-      double f[14];
-      f[0] = P.u;
-      f[1] = P.v;
-      f[2] = -SEh * g.fi_nx[fE]; f[3] = -SEh * g.fi_ny[fE];
-      f[4] = SEh * Ri[size_t(rv_lam) * nfi + fE] + SE * Ri[size_t(rv_vis) * nfi + fE];
-      f[5] = -SNh * g.fj_nx[fN]; f[6] = -SNh * g.fj_ny[fN];
-      f[7] = SNh * Rj[size_t(rv_lam) * nfj + fN] + SN * Rj[size_t(rv_vis) * nfj + fN];
-      f[8] = SWh * g.fi_nx[fW]; f[9] = SWh * g.fi_ny[fW];
-      f[10] = SWh * Ri[size_t(rv_lam) * nfi + fW] + SW * Ri[size_t(rv_vis) * nfi + fW];
-      f[11] = SSh * g.fj_nx[fS]; f[12] = SSh * g.fj_ny[fS];
-      f[13] = SSh * Rj[size_t(rv_lam) * nfj + fS] + SS * Rj[size_t(rv_vis) * nfj + fS];
+      double mx[4], my[4], cf[4], un[4];
+      mx[0] = -SEh * g.fi_nx[fE]; my[0] = -SEh * g.fi_ny[fE];
+      cf[0] = SEh * Ri[size_t(rv_lam) * nfi + fE] + SE * Ri[size_t(rv_vis) * nfi + fE];
+      mx[1] = -SNh * g.fj_nx[fN]; my[1] = -SNh * g.fj_ny[fN];
+      cf[1] = SNh * Rj[size_t(rv_lam) * nfj + fN] + SN * Rj[size_t(rv_vis) * nfj + fN];
+      mx[2] = SWh * g.fi_nx[fW]; my[2] = SWh * g.fi_ny[fW];
+      cf[2] = SWh * Ri[size_t(rv_lam) * nfi + fW] + SW * Ri[size_t(rv_vis) * nfi + fW];
+      mx[3] = SSh * g.fj_nx[fS]; my[3] = SSh * g.fj_ny[fS];
+      cf[3] = SSh * Rj[size_t(rv_lam) * nfj + fS] + SS * Rj[size_t(rv_vis) * nfj + fS];
 #pragma unroll
-      for (int k = 0; k < 14; ++k) Cf[gm.cell(blk, k, cc)] = RT(f[k]);
-      if (w)
-        for (int k = 0; k < gm.G; ++k) Cf[gm.cell(blk, CF_W + k, cc)] = RT(w[k]);
+      for (int f = 0; f < 4; ++f) un[f] = P.u * mx[f] + P.v * my[f];
+      if (!w) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) Rr[gm.cell(blk, f, cc)] = RT(un[f] - cf[f]);
+        return;
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        Rr[gm.cell(blk, 3 * f, cc)] = RT(mx[f]);
+        Rr[gm.cell(blk, 3 * f + 1, cc)] = RT(my[f]);
+        Rr[gm.cell(blk, 3 * f + 2, cc)] = RT(un[f]);
+      }
+      for (int k = 0; k < gm.G; ++k) {
+        Rr[gm.cell(blk, CF_W + k, cc)] = RT(w[k]);
+        Rr[gm.lane(blk, LF_CA, cc, k)] = RT(ca[k]);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const double cp = k == 1 ? mx[f] : k == 2 ? my[f] : k == 3 ? un[f] : 0.0;
+          Rr[gm.lane(blk, LF_FACE + 2 * f, cc, k)] = RT((k > 0 ? un[f] : 0.0) - cf[f]);
+          Rr[gm.lane(blk, LF_FACE + 2 * f + 1, cc, k)] = RT(cp);
+        }
+      }
     };
     if (mode == 0) {
       // coupled: dS_z/dz, z = (rho, m_x, m_y, rhoE, [rhoe_ve], rho_0..rho_{ns-2})
@@ -638,12 +665,11 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-          L[gm.lane(blk, 0, cc, r)] = RT(bz[r]);
-          L[gm.lane(blk, 1, cc, r)] = RT(ca[r]);
+          L[gm.lane(blk, LF_B, cc, r)] = RT(bz[r]);
 #pragma unroll
           for (int c = 0; c < NB; ++c) L[gm.drow(blk, c, cc, r)] = RT(Ai[r][c]);
         }
-        write_cells(0, PART_COUPLED, R_LAM, R_LVK, w);
+        write_push(0, PART_COUPLED, R_LAM, R_LVK, w, ca);
       }
     } else {
       double dF = Vdt + 0.5 * slam + svF;
@@ -739,12 +765,11 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
           }
 #pragma unroll
           for (int r = 0; r < NF; ++r) {
-            L[gm.lane(blk, 0, cc, r)] = RT(bf[r]);
-            L[gm.lane(blk, 1, cc, r)] = RT(ca[r]);
+            L[gm.lane(blk, LF_B, cc, r)] = RT(bf[r]);
 #pragma unroll
             for (int c = 0; c < NF; ++c) L[gm.drow(blk, c, cc, r)] = RT(Df[r][c]);
           }
-          write_cells(0, PART_FLOW, R_LAM, R_LVF, w);
+          write_push(0, PART_FLOW, R_LAM, R_LVF, w, ca);
         }
         // species part
         {
@@ -758,7 +783,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
             for (int c = 0; c < NS; ++c) L[gm.drow(blk, c, cc, r)] = RT(Ai[r][c]);
           }
-          write_cells(1, PART_SPECIES, R_UABS, R_LVC, nullptr);
+          write_push(1, PART_SPECIES, R_UABS, R_LVC, nullptr, nullptr);
         }
       }
     }
