@@ -100,17 +100,18 @@ size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 // wave): the larger of the two element sizes (the precision can change after
 // binding)
 struct GroupCap {
-  size_t R = 0, x = 0, bnd = 0;
-  void merge(const GroupCap &o) { R = std::max(R, o.R); x = std::max(x, o.x); bnd = std::max(bnd, o.bnd); }
+  size_t S = 0, x = 0, bnd = 0;
+  void merge(const GroupCap &o) { S = std::max(S, o.S); x = std::max(x, o.x); bnd = std::max(bnd, o.bnd); }
 };
-GroupCap group_cap(int ni, int nj, PartShape p) {
+GroupCap group_cap(int ni, int nj, int part, int ns, int nt) {
   GroupCap r;
   for (int esz = 4; esz <= 8; esz += 4) {
-    const GroupMap m = group_map(ni, nj, p, 64 / p.G, esz);
+    const RecShape rs = rec_shape(part, ns, nt, esz);
+    const GroupMap m = group_map(ni, nj, rs.G);
     GroupCap t;
-    t.R = size_t(m.nblk) * m.RW * esz;
+    t.S = size_t(st_words(rs, long(ni) * nj)) * esz;
     t.x = size_t(m.nblk) * m.Lw * esz;
-    t.bnd = size_t(m.nstrip) * nj * p.G * esz;
+    t.bnd = size_t(m.nstrip) * nj * rs.G * esz;
     r.merge(t);
   }
   return r;
@@ -128,9 +129,9 @@ Layout layout(const csi_ctx *c, int nprim) {
   const size_t nblk = (N + 255) / 256;
   const size_t A = N;
   // group-schedule records, per part
-  GroupCap g0 = group_cap(c->ni, c->nj, part_shape(PART_COUPLED, c->ns, c->nt));
-  g0.merge(group_cap(c->ni, c->nj, part_shape(PART_FLOW, c->ns, c->nt)));
-  const GroupCap g1 = group_cap(c->ni, c->nj, part_shape(PART_SPECIES, c->ns, c->nt));
+  GroupCap g0 = group_cap(c->ni, c->nj, PART_COUPLED, c->ns, c->nt);
+  g0.merge(group_cap(c->ni, c->nj, PART_FLOW, c->ns, c->nt));
+  const GroupCap g1 = group_cap(c->ni, c->nj, PART_SPECIES, c->ns, c->nt);
   const MlpDims sd = mlp_dims(c->ns + 3, c->ns * c->ns);
   size_t sizes[] = {
       sizeof(Mech),                       // 0 mech
@@ -148,8 +149,8 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(nsol) * A * 8, size_t(nsol) * A * 8, size_t(nsol) * A * 8,  // 27-29 b dqs dq (hyperplane schedule)
       ndinv * A * 8,                                  // 30 Dinv (hyperplane schedule)
       FL_N * 4,                                       // 31 flags
-      g0.R, g0.x, g0.bnd, g0.bnd, 8,                  // 32-36 group part 0: records, dQ, pushes (fwd, bwd), tickets
-      g1.R, g1.x, g1.bnd, g1.bnd, 8,                  // 37-41 group part 1
+      g0.S, g0.x, g0.bnd, g0.bnd, 8,                  // 32-36 group part 0: record staging, dQ, pushes (fwd, bwd), tickets
+      g1.S, g1.x, g1.bnd, g1.bnd, 8,                  // 37-41 group part 1
       size_t(c->ns) * c->ns * N * 4,                  // 42 surrogate J_C
       size_t(sd.nslots) * 16,                         // 43 surrogate packed operands
       size_t(sd.np) * 4,                              // 44 surrogate FP32 parameters
@@ -320,7 +321,7 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   for (int q = 0; q < 2; ++q) {
     const int o = 32 + 5 * q;
     GroupBufs &gb = w.grp[q];
-    gb.R = b + L.off[o];
+    gb.S = b + L.off[o];
     gb.x = b + L.off[o + 1];
     gb.bnd[0] = b + L.off[o + 2];
     gb.bnd[1] = b + L.off[o + 3];
@@ -682,27 +683,28 @@ int get_records(csi_ctx *c, const std::string &n, double *out, size_t count) {
     std::copy(h.begin() + 6 * N, h.end(), out + size_t(nf) * nf * N);
     return CSI_OK;
   }
-  // group schedule
+  // group schedule: staging (b, D^-1, dQ*) and the step-blocked dQ
   const int nparts = coupled ? 1 : 2;
   size_t fo = 0;  // first output field of the part
   for (int q = 0; q < nparts; ++q) {
-    const PartShape ps = part_shape(q == 1 ? PART_SPECIES : coupled ? PART_COUPLED : PART_FLOW, ns, c->nt);
-    const int G = ps.G;
-    const GroupMap m = group_map(c->ni, c->nj, ps, 64 / G, int(esz));
+    const RecShape rs = rec_shape(q == 1 ? PART_SPECIES : coupled ? PART_COUPLED : PART_FLOW, ns, c->nt, int(esz));
+    const int G = rs.G;
+    const GroupMap m = group_map(c->ni, c->nj, G);
     const GroupBufs &gb = c->w.grp[q];
     const bool res = n == "dq";
-    if (int rc = fetch(res ? gb.x : gb.R, size_t(m.nblk) * (res ? m.Lw : m.RW), h)) return rc;
+    if (int rc = fetch(res ? gb.x : gb.S, res ? size_t(m.nblk) * m.Lw : size_t(st_words(rs, long(N))), h)) return rc;
     const int nout = dinv ? G * G : G;
     for (int j = 0; j < c->nj; ++j)
       for (int i = 0; i < c->ni; ++i) {
         int cc;
         const long blk = group_blk(m, i, j, cc);
-        const size_t p = size_t(j) * c->ni + i;
+        const long p = long(j) * c->ni + i;
         for (int f = 0; f < nout; ++f) {
           const int r = dinv ? f / G : f, col = dinv ? f % G : 0;
-          const long k = dinv ? m.drow(blk, col, cc, r) : n == "b" ? m.lane(blk, 0, cc, r)
-                                                       : n == "dqs" ? m.xs(blk, cc, r) : m.res(blk, cc, r);
-          out[(fo + f) * N + p] = h[size_t(k)];
+          const long k = dinv ? st_idx(rs, long(N), 0, rw_d(rs, r, col), p)
+                              : n == "b" ? st_idx(rs, long(N), 1, dw_b(r), p)
+                                         : n == "dqs" ? st_idx(rs, long(N), 2, dw_b(r), p) : m.res(blk, cc, r);
+          out[(fo + f) * N + size_t(p)] = h[size_t(k)];
         }
       }
     fo += nout;

@@ -19,8 +19,9 @@
 // latency, not bandwidth.  The workgroup therefore has three wavefronts, so
 // that the compute wave never waits for global memory:
 //   wave 0  computes; it reads its step records from an LDS ring;
-//   wave 1  streams the step records into the ring with global-to-LDS copies
-//           (whole KiB per instruction), up to a ring of DEPTH steps ahead;
+//   wave 1  gathers the records of the step's C cells from the staging
+//           array into the ring with 16-byte global-to-LDS copies, up to a
+//           ring of DEPTH steps ahead;
 //   wave 2  takes the pushes that cross the strip boundary (written by the
 //           neighbouring strip's compute wave) and hands them over in LDS.
 // A boundary push is its own ready flag: its slot is filled with an all-ones
@@ -38,8 +39,8 @@ namespace csi {
 
 // device buffers of one part (inside the workspace)
 struct GroupBufs {
-  void *R;        // step records (RT), see the record layout
-  void *x;        // backward results dQ (RT) [blk][C G]
+  void *S;        // record staging (RT), written by the cell kernel (dQ* by the forward sweep)
+  void *x;        // backward results dQ (RT) [blk][G C]
   void *bnd[2];   // boundary pushes of the forward / backward sweep, RT [nstrip][nj][G]
   int *tickets;   // [2] strip tickets of the forward / backward sweep
 };
@@ -58,13 +59,17 @@ struct GroupArgs {
 // the copy wave on free ring slots and of the boundary wave on pushes
 enum { TR_T0 = 0, TR_T1, TR_REC, TR_BND, TR_COPY, TR_POLL, TR_N = 8 };
 
-// ring geometry of a part: KB KiB per step record, DEPTH slots, at most LAG
-// steps of copies in flight (LAG KB copy instructions <= 60: the vector
-// memory counter has 6 bits)
+// Ring geometry of a part and sweep direction.  A step's LDS block holds the
+// C cells' common and direction sections, cell c at granule c NQ: KB copy
+// instructions (1 KiB each) per step, DEPTH slots, at most LAG steps of
+// copies in flight (LAG KB <= 60: the vector memory counter has 6 bits).
 template <int NS, int NT, typename RT, int P> struct GPipe {
-  static constexpr PartShape S = part_shape(P, NS, NT);
-  static constexpr int G = S.G;
-  static constexpr int KB = group_kib(S, sizeof(RT));
+  static constexpr RecShape S = rec_shape(P, NS, NT, sizeof(RT));
+  static constexpr int G = S.G, C = 64 / G, GW = S.GW;
+  static constexpr int NQ = S.QC + S.QD;               // granules per cell in LDS
+  static constexpr int CS = NQ * GW;                   // words per cell in LDS
+  static constexpr int KB = (C * NQ + 63) / 64;
+  static constexpr int SLOT = KB * 1024 / int(sizeof(RT));  // words per step block
   static constexpr int DEPTH = 128 / KB < 16 ? 128 / KB : 16;
   static constexpr int LAG = 60 / KB < DEPTH - 1 ? 60 / KB : DEPTH - 1;
   static constexpr size_t RING = size_t(DEPTH) * KB * 1024;
@@ -155,46 +160,41 @@ __device__ __forceinline__ bool take_push(const RT *p, RT &v, int *abort_flag, l
 // position in the unrolled loop (results do not depend on C).
 template <typename RT> __device__ __forceinline__ RT fmad(RT a, RT b, RT c) { return fma(a, b, c); }
 
-// compile-time layout of one step block (C = 64 / G cells per wave)
-template <int NS, int NT, int P> struct GLayout {
-  static constexpr PartShape S = part_shape(P, NS, NT);
-  static constexpr int G = S.G, C = 64 / G, Lw = G * C, FL = S.FL, FC = S.FC;
-  static constexpr int OX = FL * Lw, OD = OX + Lw, OC = OD + G * Lw;  // dQ*, D^-1 rows, cell fields
-};
-
 // per-step record of one lane.  The forward sweep pushes through faces E, N,
 // the backward sweep through W, S.
 template <int NS, int NT, typename RT, int P, bool FWD> struct GRec {
-  using Gp = GPart<NS, NT, P>;
-  using Ly = GLayout<NS, NT, P>;
-  static constexpr int G = Gp::G, F0 = FWD ? 0 : 2;
+  using Pp = GPipe<NS, NT, RT, P>;
+  static constexpr RecShape S = Pp::S;
+  static constexpr int G = S.G, OD = S.QC * S.GW;  // direction section of a cell in LDS
+  static constexpr bool JVP = P != PART_SPECIES;
   RT b;          // forward: RHS b_k; backward: dQ*_k
   RT Dr[G];      // row k of D^-1
   // JVP parts: coefficient of a, and per push face: g_k, cp_k, (m_x, m_y, u.m), dp weights
   RT ca, gk[2], cp[2], mx[2], my[2], un[2];
-  RT w[Gp::JVP ? G : 1];
+  RT w[JVP ? G : 1];
   RT coef[2];    // species part: u.m - c per push face
 
-  // from one step block in LDS: L = block + k C + c (lane fields), Q = block + OC + c (cell fields)
-  __device__ __forceinline__ void load(const RT *L, const RT *Q) {
-    b = FWD ? L[0] : L[Ly::OX];
+  // from one step block in LDS: Q = the cell's record (block + c CS), component k
+  __device__ __forceinline__ void load(const RT *Q, int k) {
+    const RT *L = Q + k, *DL = Q + k * G;
+    b = L[OD + dw_b(0)];
 #pragma unroll
-    for (int q = 0; q < G; ++q) Dr[q] = L[Ly::OD + q * Ly::Lw];
-    if (Gp::JVP) {
-      ca = L[LF_CA * Ly::Lw];
+    for (int q = 0; q < G; ++q) Dr[q] = DL[q];
+    if (JVP) {
+      ca = L[rw_ca(S, 0)];
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        gk[f] = L[(LF_FACE + 2 * (F0 + f)) * Ly::Lw];
-        cp[f] = L[(LF_FACE + 2 * (F0 + f) + 1) * Ly::Lw];
-        mx[f] = Q[3 * (F0 + f) * Ly::C];
-        my[f] = Q[(3 * (F0 + f) + 1) * Ly::C];
-        un[f] = Q[(3 * (F0 + f) + 2) * Ly::C];
+        gk[f] = L[OD + dw_g(S, f, 0)];
+        cp[f] = L[OD + dw_cp(S, f, 0)];
+        mx[f] = Q[OD + dw_m(S, f)];
+        my[f] = Q[OD + dw_m(S, f) + 1];
+        un[f] = Q[OD + dw_m(S, f) + 2];
       }
 #pragma unroll
-      for (int q = 0; q < G; ++q) w[q] = Q[(CF_W + q) * Ly::C];
+      for (int q = 0; q < G; ++q) w[q] = Q[rw_w(S, q)];
     } else {
 #pragma unroll
-      for (int f = 0; f < 2; ++f) coef[f] = Q[(F0 + f) * Ly::C];
+      for (int f = 0; f < 2; ++f) coef[f] = Q[OD + dw_coef(S, f)];
     }
   }
 };
@@ -249,11 +249,27 @@ struct GroupSync {
   int consumed;   // steps whose ring slots the compute wave has read
 };
 
-// wave 1: step records of the strip, in sweep order, into the LDS ring
-template <int KB, int DEPTH, int LAG>
-__device__ __forceinline__ long copy_wave(const char *R, long blk0, int dir, int NSTEP, char *ring, GroupSync &sy,
+// wave 1: the records of each step's cells, in sweep order, gathered from
+// the staging array into the LDS ring.  Copy instruction q of lane l moves
+// granule n = 64 q + l of the step block: cell c = n / NQ, granule n % NQ of
+// its common then direction section.  Cells outside the grid read a clamped
+// (valid) cell; their lanes' results are discarded.
+template <int NS, int NT, typename RT, int P, bool FWD>
+__device__ __forceinline__ long copy_wave(const Geo &g, const RT *stage, int s, int NSTEP, char *ring, GroupSync &sy,
                                           int *abort_flag, long spin_limit) {
+  using Pp = GPipe<NS, NT, RT, P>;
+  constexpr RecShape S = Pp::S;
+  constexpr int KB = Pp::KB, DEPTH = Pp::DEPTH, LAG = Pp::LAG, NQ = Pp::NQ, C = Pp::C;
   const int lane = threadIdx.x & 63;
+  const char *base = reinterpret_cast<const char *>(stage);
+  constexpr int QR = S.QC + 2 * S.QD;  // granules per staged record
+  int col[KB], gofs[KB];  // the lane's cell column and granule within the record
+#pragma unroll
+  for (int q = 0; q < KB; ++q) {
+    const int n = q * 64 + lane, c = n / NQ, r = n - c * NQ;
+    col[q] = c < C ? c : -1;
+    gofs[q] = r < S.QC ? r : S.QC + (FWD ? 0 : S.QD) + (r - S.QC);
+  }
   int pub = 0, seen = 0, slot = 0;
   long spins = 0;
   for (int e = 0; e < NSTEP; ++e) {
@@ -271,12 +287,15 @@ __device__ __forceinline__ long copy_wave(const char *R, long blk0, int dir, int
       }
       spins += n;
     }
-    const char *src = R + (blk0 + long(dir) * e) * (KB * 1024L) + lane * 16;
+    const int d = FWD ? e : NSTEP - 1 - e;
     char *dst = ring + slot * (KB * 1024);
 #pragma unroll
-    for (int q = 0; q < KB; ++q)
-      __builtin_amdgcn_global_load_lds(src + q * 1024,
-                                       (__attribute__((address_space(3))) void *)(dst + q * 1024), 16, 0, 0);
+    for (int q = 0; q < KB; ++q) {
+      const int c = col[q] < 0 ? 0 : col[q];
+      const int i = min(s * C + c, g.ni - 1), j = min(max(d - c, 0), g.nj - 1);
+      const char *src = base + ((long(j) * g.ni + i) * QR + gofs[q]) * 16;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + q * 1024), 16, 0, 0);
+    }
     if (++slot == DEPTH) slot = 0;
     if (e >= LAG) {
       // copies of step e - LAG have landed once at most LAG steps of copies are in flight
@@ -378,10 +397,10 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
                                              long &rsp, long &bsp) {
 #pragma clang fp contract(off)
   using Pp = GPipe<NS, NT, RT, P>;
-  using Ly = GLayout<NS, NT, P>;
   using R = GRec<NS, NT, RT, P, FWD>;
-  constexpr int G = Pp::G, DEPTH = Pp::DEPTH, SLOT = Pp::KB * 1024 / int(sizeof(RT)), C = Ly::C;
-  constexpr bool JVP = GPart<NS, NT, P>::JVP;
+  constexpr RecShape S = Pp::S;
+  constexpr int G = Pp::G, DEPTH = Pp::DEPTH, SLOT = Pp::SLOT, C = Pp::C;
+  constexpr bool JVP = R::JVP;
   const int lane = threadIdx.x & 63;
   const int NSTEP = m.NSTEP;
   const int k = lane / C, c = lane - k * C;
@@ -392,7 +411,8 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
   int gaddr[G];  // byte addresses of the group's lanes (q C + c)
 #pragma unroll
   for (int q = 0; q < G; ++q) gaddr[q] = (q * C + c) * 4;
-  RT *out = reinterpret_cast<RT *>(FWD ? gp.b.R : gp.b.x);
+  // forward: dQ* into the staging (backward section); backward: dQ step-blocked
+  RT *out = reinterpret_cast<RT *>(FWD ? gp.b.S : gp.b.x);
   RT *bnd = reinterpret_cast<RT *>(gp.b.bnd[FWD ? 0 : 1]);
   const long b0 = long(s) * NSTEP;
   // the column that takes a push from the neighbouring strip
@@ -404,12 +424,12 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
   // the backward sweep the last column of the grid (its east neighbour is padding)
   const bool no_src = c == edge || (!FWD && i + 1 >= g.ni);
   const RT beta = k == 0 ? RT(1) : RT(0);
-  const int lofs = kk * C + c, cofs = Ly::OC + c;
+  const int cofs = c * Pp::CS;  // the cell's record in a step block
   bool live = true;
   int rec_seen = lds_spin(&sy.rec_ready, 1, a.abort_flag, a.spin_limit, rsp, live);
   int bnd_seen = 0;
   R A, B;
-  A.load(ring + lofs, ring + cofs);
+  A.load(ring + cofs, kk);
   RT in1 = RT(0), in2 = RT(0);  // pushes from the west / south (forward), east / north (backward)
   int slot = 0;
   auto step = [&](int e, R &cur, R &nxt) {
@@ -435,8 +455,7 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
     const int nslot = slot + 1 == DEPTH ? 0 : slot + 1;
     if (e + 1 < NSTEP) {
       if (rec_seen <= e + 1) rec_seen = lds_spin(&sy.rec_ready, e + 2, a.abort_flag, a.spin_limit, rsp, live);
-      const RT *S = ring + nslot * SLOT;
-      nxt.load(S + lofs, S + cofs);
+      nxt.load(ring + nslot * SLOT + cofs, kk);
     }
     lds_set(&sy.consumed, e + 1);
     slot = nslot;
@@ -462,9 +481,14 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
     // The pushes of a cell outside the grid reach only cells outside the grid
     // (the same j, or i beyond the last column), except the in-column push
     // into the first cell of the column, which h2 excludes, and the backward
-    // push from beyond the last column, which no_src excludes; results
-    // outside the grid land in padding slots of the step blocks.
-    if (lane_ok) out[FWD ? (b0 + d) * SLOT + Ly::OX + k * C + c : (b0 + d) * Ly::Lw + k * C + c] = x;
+    // push from beyond the last column, which no_src excludes.  Backward
+    // results outside the grid land in padding slots of the step blocks.
+    const bool active = col_ok && j >= 0 && j < g.nj;
+    if (FWD) {
+      if (active) out[st_idx(S, g.N, 2, dw_b(k), long(j) * g.ni + i)] = x;
+    } else if (lane_ok) {
+      out[(b0 + d) * m.Lw + k * C + c] = x;
+    }
     if (send_nb && j >= 0 && j < g.nj) put_push(bnd + (long(FWD ? s : s - 1) * g.nj + j) * G + k, p1);
     in1 = lane_move<FWD>(p1);
     in1 = no_src ? RT(0) : in1;
@@ -482,7 +506,7 @@ __device__ __forceinline__ void group_part(const Geo &g, const GroupArgs &a, int
   using Pp = GPipe<NS, NT, RT, P>;
   constexpr int G = Pp::G;
   const GroupPart &gp = a.part[q];
-  const GroupMap m = group_map(g.ni, g.nj, Pp::S, gp.C, sizeof(RT));
+  const GroupMap m = group_map(g.ni, g.nj, G);
   if (threadIdx.x == 0) {
     sy.strip = FWD ? atomicAdd(gp.b.tickets, 1) : m.nstrip - 1 - atomicAdd(gp.b.tickets + 1, 1);
     sy.rec_ready = 0;
@@ -499,9 +523,8 @@ __device__ __forceinline__ void group_part(const Geo &g, const GroupArgs &a, int
   long long *tr = a.trace ? a.trace + (long(q) * g.ni + s) * TR_N : nullptr;
   const int lane = threadIdx.x & 63;
   if (wave == 1) {
-    const long sp = copy_wave<Pp::KB, Pp::DEPTH, Pp::LAG>(reinterpret_cast<const char *>(gp.b.R),
-                                                          FWD ? b0 : b0 + m.NSTEP - 1, FWD ? 1 : -1, m.NSTEP, lds, sy,
-                                                          a.abort_flag, a.spin_limit);
+    const long sp = copy_wave<NS, NT, RT, P, FWD>(g, reinterpret_cast<const RT *>(gp.b.S), s, m.NSTEP, lds, sy,
+                                                  a.abort_flag, a.spin_limit);
     if (tr && lane == 0) tr[TR_COPY] = sp;
   } else if (wave == 2) {
     const RT *bnd = reinterpret_cast<const RT *>(gp.b.bnd[FWD ? 0 : 1]);

@@ -383,78 +383,70 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
 
 // ----------------------------------------------- group-schedule record layout
 // The sweeps give each cell a group of G lanes (one per unknown of the swept
-// part) and each wavefront a strip of C <= 64 / G columns.  Records are
-// stored in step blocks blk = s NSTEP + d (strip s, step d = i - i0 + j,
-// NSTEP = nj + C - 1); one block is contiguous so that a sweep wave can copy
-// it to LDS with whole-KiB transfers:
-//   lane fields  [F_L][G C]   lane (c, k) at k C + c: RHS b_k; JVP parts also the
-//                             coefficients of the push (see the sweeps)
-//   dQ*          [G C]        written by the forward sweep for the backward sweep
-//   D^-1 rows    [G][G C]     (D^-1)_km at lane (c, k), field m
-//   cell fields  [F_C][C]     per face E, N, W, S: JVP parts the scaled normal and
-//                             u.m, then the dp weights; species part u.m - c
-// padded to a whole number of KiB (the size at C = 64 / G, so the stride does
-// not depend on C).  The backward results dQ are a separate array [blk][G C].
-// Lanes are component-major (k C + c), so that the push of column c reaches
-// column c + 1 (same component) one lane up.
+// part) and each wavefront a strip of C = 64 / G columns.  The cell kernel
+// writes a record per cell and part into a staging array; each sweep step
+// gathers the records of the C cells it works on into LDS with 16-byte
+// global-to-LDS copies.  A record has three sections (words of RT):
+//   common    D^-1 row-major [G][G]; JVP parts also the dp weights w[G] and
+//             the coefficients of a, ca[G]
+//   forward   RHS b[G]; JVP parts per push face (E, N): g[G], cp[G], then per
+//             face (m_x, m_y, u.m); species part per face u.m - c
+//   backward  dQ*[G] (written by the forward sweep), then as forward for the
+//             faces W, S
+// Each section is padded to whole 16-byte granules (GW words); the staging
+// array holds the records one after the other (cell p at p (QC + 2 QD) GW),
+// so that a sweep step reads each cell's sections as contiguous runs.
 
 // parts of the implicit operator swept by one wavefront
 enum { PART_COUPLED = 0, PART_FLOW = 2, PART_SPECIES = 3 };
-// lane fields of the JVP parts: b, ca, then (g, cp) per face E, N, W, S;
-// cell fields: (m_x, m_y, u.m) per face, then the dp weights
-enum { LF_B = 0, LF_CA = 1, LF_FACE = 2, CF_W = 12 };
 
-// lanes per cell, lane fields, cell fields of a part
-struct PartShape {
-  int G, FL, FC;
+struct RecShape {
+  int G, JVP;   // lanes per cell, whether the push is a flux Jacobian-vector product
+  int CW, DW;   // words of the common and of each direction section
+  int GW;       // words per 16-byte granule
+  int QC, QD;   // granules of the common and of each direction section
 };
-__host__ __device__ constexpr PartShape part_shape(int part, int ns, int nt) {
+__host__ __device__ constexpr RecShape rec_shape(int part, int ns, int nt, int esz) {
   const int nf = nt == 2 ? 5 : 4, nb = nf + ns - 1;
-  return part == PART_COUPLED ? PartShape{nb, 10, CF_W + nb} : part == PART_FLOW ? PartShape{nf, 10, CF_W + nf}
-                                                                                 : PartShape{ns, 1, 4};
+  const int G = part == PART_COUPLED ? nb : part == PART_FLOW ? nf : ns;
+  const int jvp = part != PART_SPECIES;
+  const int CW = G * G + (jvp ? 2 * G : 0), DW = G + (jvp ? 4 * G + 6 : 2), GW = 16 / esz;
+  return RecShape{G, jvp, CW, DW, GW, (CW + GW - 1) / GW, (DW + GW - 1) / GW};
 }
-// KiB per step record (element size esz)
-__host__ __device__ constexpr int group_kib(PartShape p, int esz) {
-  const int CM = 64 / p.G;
-  const long used = long(p.FL + 1 + p.G) * CM * p.G + long(p.FC) * CM;
-  return int((used * esz + 1023) / 1024);
+// word offsets: common section
+__host__ __device__ constexpr int rw_d(const RecShape &r, int k, int q) { return k * r.G + q; }
+__host__ __device__ constexpr int rw_w(const RecShape &r, int q) { return r.G * r.G + q; }
+__host__ __device__ constexpr int rw_ca(const RecShape &r, int k) { return r.G * r.G + r.G + k; }
+// direction sections (face f = 0, 1: E, N forward; W, S backward)
+__host__ __device__ constexpr int dw_b(int k) { return k; }
+__host__ __device__ constexpr int dw_g(const RecShape &r, int f, int k) { return r.G + 2 * f * r.G + k; }
+__host__ __device__ constexpr int dw_cp(const RecShape &r, int f, int k) { return r.G + (2 * f + 1) * r.G + k; }
+__host__ __device__ constexpr int dw_m(const RecShape &r, int f) { return 5 * r.G + 3 * f; }  // m_x, m_y, u.m
+__host__ __device__ constexpr int dw_coef(const RecShape &r, int f) { return r.G + f; }      // species
+// staging element of word W of section sec (0 common, 1 forward, 2 backward) of cell p
+__host__ __device__ constexpr long st_idx(const RecShape &r, long N, int sec, int W, long p) {
+  return (p * (r.QC + 2 * r.QD) + (sec == 0 ? 0 : sec == 1 ? r.QC : r.QC + r.QD)) * r.GW + W;
 }
+__host__ __device__ constexpr long st_words(const RecShape &r, long N) { return long(r.QC + 2 * r.QD) * N * r.GW; }
 
-template <int NS, int NT, int P> struct GPart {
-  static constexpr PartShape S = part_shape(P, NS, NT);
-  static constexpr int G = S.G, FL = S.FL, FC = S.FC;
-  static constexpr int CMAX = 64 / G;          // cells per wave
-  static constexpr bool JVP = P != PART_SPECIES;
-};
-
-// step-block geometry of one part
+// strip geometry of one part
 struct GroupMap {
-  int G, C, NSTEP, nstrip, Lw, FL, FC, RW;     // RW: record stride in elements
+  int G, C, NSTEP, nstrip, Lw;
   long nblk;
-  __host__ __device__ long lane(long blk, int f, int c, int k) const { return blk * RW + long(f) * Lw + k * C + c; }
-  __host__ __device__ long xs(long blk, int c, int k) const { return blk * RW + long(FL) * Lw + k * C + c; }
-  __host__ __device__ long drow(long blk, int q, int c, int k) const {
-    return blk * RW + long(FL + 1 + q) * Lw + k * C + c;
-  }
-  __host__ __device__ long cell(long blk, int f, int c) const {
-    return blk * RW + long(FL + 1 + G) * Lw + long(f) * C + c;
-  }
+  // backward results dQ, step-blocked [blk][G C], lane (c, k) at k C + c
   __host__ __device__ long res(long blk, int c, int k) const { return blk * Lw + k * C + c; }
 };
-__host__ __device__ inline GroupMap group_map(int ni, int nj, PartShape p, int C, int esz) {
+__host__ __device__ inline GroupMap group_map(int ni, int nj, int G) {
   GroupMap m;
-  m.G = p.G;
-  m.C = C;
-  m.FL = p.FL;
-  m.FC = p.FC;
-  m.NSTEP = nj + C - 1;
-  m.nstrip = (ni + C - 1) / C;
-  m.Lw = C * p.G;
-  m.RW = group_kib(p, esz) * 1024 / esz;
+  m.G = G;
+  m.C = 64 / G;
+  m.NSTEP = nj + m.C - 1;
+  m.nstrip = (ni + m.C - 1) / m.C;
+  m.Lw = m.C * G;
   m.nblk = long(m.nstrip) * m.NSTEP;
   return m;
 }
-// block and column of cell (i, j)
+// block and column of cell (i, j): block s NSTEP + d, d = j + c
 __host__ __device__ inline long group_blk(const GroupMap &m, int i, int j, int &c) {
   const int s = i / m.C;
   c = i - s * m.C;
@@ -471,11 +463,10 @@ struct CellOut {
   double *R, *dtau, *part;     // part: per-block norm partials [2][nblocks]
   void *Dinv;                  // coupled: nb*nb fields; split: DF 6 fields then DC ns*ns fields
   void *b;                     // RHS, nsol fields
-  void *gR[2];                 // group schedule records of part 0 (coupled / flow) and 1 (species)
+  void *gS[2];                 // group schedule: record staging of part 0 (coupled / flow) and 1 (species)
   double *src;                 // optional source vector [nv][N] (debug)
   int *bad;
   int group_c;                 // 0: hyperplane schedule (cell-major records); > 0: group schedule
-  int group_cp[2];             // cells per wave of each part (group schedule)
   const float *Jsur;           // surrogate J_C [ns * ns][N] (flags bit 4)
   unsigned long long *ddfail;  // count of cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off (stall), use the exact block
@@ -559,7 +550,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     {
     // temperature derivatives w.r.t. stored variables (recomputed from the state)
     Prim<NS, NT> P;
-    prim_from_q<NS, NT>(m, q, P);
+    prim_from_q<NS, NT>(m, q, P, T, Tv);  // T, Tv: k_prim's solution for this q
     double Vdt = Vp / dt;
     // hyperplane schedule: cell-major records (field f at f N + p)
     const bool grp = out.group_c > 0;
@@ -576,10 +567,9 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     //   g_k = [k > 0] u.m - c,  cp_k = (0, m_x, m_y, u.m, 0, ...)_k;
     // species part: u.m - c per face.
     auto write_push = [&](int q, int part, int rv_lam, int rv_vis, const double *w, const double *ca) {
-      RT *Rr = reinterpret_cast<RT *>(out.gR[q]);
-      const GroupMap gm = group_map(g.ni, g.nj, part_shape(part, NS, NT), out.group_cp[q], sizeof(RT));
-      int cc;
-      const long blk = group_blk(gm, i, j, cc);
+      RT *St = reinterpret_cast<RT *>(out.gS[q]);
+      const RecShape S = rec_shape(part, NS, NT, sizeof(RT));
+      auto put = [&](int sec, int W, double v) { St[st_idx(S, g.N, sec, W, p)] = RT(v); };
       double mx[4], my[4], cf[4], un[4];
       mx[0] = -SEh * g.fi_nx[fE]; my[0] = -SEh * g.fi_ny[fE];
       cf[0] = SEh * Ri[size_t(rv_lam) * nfi + fE] + SE * Ri[size_t(rv_vis) * nfi + fE];
@@ -591,25 +581,26 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
       cf[3] = SSh * Rj[size_t(rv_lam) * nfj + fS] + SS * Rj[size_t(rv_vis) * nfj + fS];
 #pragma unroll
       for (int f = 0; f < 4; ++f) un[f] = P.u * mx[f] + P.v * my[f];
+      // face f of the forward (f < 2) or backward section
       if (!w) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) Rr[gm.cell(blk, f, cc)] = RT(un[f] - cf[f]);
+        for (int f = 0; f < 4; ++f) put(1 + f / 2, dw_coef(S, f % 2), un[f] - cf[f]);
         return;
       }
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        Rr[gm.cell(blk, 3 * f, cc)] = RT(mx[f]);
-        Rr[gm.cell(blk, 3 * f + 1, cc)] = RT(my[f]);
-        Rr[gm.cell(blk, 3 * f + 2, cc)] = RT(un[f]);
+        put(1 + f / 2, dw_m(S, f % 2), mx[f]);
+        put(1 + f / 2, dw_m(S, f % 2) + 1, my[f]);
+        put(1 + f / 2, dw_m(S, f % 2) + 2, un[f]);
       }
-      for (int k = 0; k < gm.G; ++k) {
-        Rr[gm.cell(blk, CF_W + k, cc)] = RT(w[k]);
-        Rr[gm.lane(blk, LF_CA, cc, k)] = RT(ca[k]);
+      for (int k = 0; k < S.G; ++k) {
+        put(0, rw_w(S, k), w[k]);
+        put(0, rw_ca(S, k), ca[k]);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const double cp = k == 1 ? mx[f] : k == 2 ? my[f] : k == 3 ? un[f] : 0.0;
-          Rr[gm.lane(blk, LF_FACE + 2 * f, cc, k)] = RT((k > 0 ? un[f] : 0.0) - cf[f]);
-          Rr[gm.lane(blk, LF_FACE + 2 * f + 1, cc, k)] = RT(cp);
+          put(1 + f / 2, dw_g(S, f % 2, k), (k > 0 ? un[f] : 0.0) - cf[f]);
+          put(1 + f / 2, dw_cp(S, f % 2, k), cp);
         }
       }
     };
@@ -648,10 +639,8 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
           for (int c = 0; c < NB; ++c) Dcm[long(r * NB + c) * g.N + p] = RT(Ai[r][c]);
         }
       } else {
-        const GroupMap gm = group_map(g.ni, g.nj, part_shape(PART_COUPLED, NS, NT), out.group_cp[0], sizeof(RT));
-        int cc;
-        const long blk = group_blk(gm, i, j, cc);
-        RT *L = reinterpret_cast<RT *>(out.gR[0]);
+        constexpr RecShape S = rec_shape(PART_COUPLED, NS, NT, sizeof(RT));
+        RT *St = reinterpret_cast<RT *>(out.gS[0]);
         // coefficient of a = dmn - un x_0 in each JVP component, and the dp weights
         double ca[NB], w[NB];
         ca[0] = 0.0; ca[1] = P.u; ca[2] = P.v; ca[3] = P.H;
@@ -665,9 +654,9 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-          L[gm.lane(blk, LF_B, cc, r)] = RT(bz[r]);
+          St[st_idx(S, g.N, 1, dw_b(r), p)] = RT(bz[r]);
 #pragma unroll
-          for (int c = 0; c < NB; ++c) L[gm.drow(blk, c, cc, r)] = RT(Ai[r][c]);
+          for (int c = 0; c < NB; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
         }
         write_push(0, PART_COUPLED, R_LAM, R_LVK, w, ca);
       }
@@ -743,10 +732,8 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
       } else {
         // flow part: its inverse written as a dense nf x nf block
         {
-          const GroupMap gm = group_map(g.ni, g.nj, part_shape(PART_FLOW, NS, NT), out.group_cp[0], sizeof(RT));
-          int cc;
-          const long blk = group_blk(gm, i, j, cc);
-          RT *L = reinterpret_cast<RT *>(out.gR[0]);
+          constexpr RecShape S = rec_shape(PART_FLOW, NS, NT, sizeof(RT));
+          RT *St = reinterpret_cast<RT *>(out.gS[0]);
           double prY = 0.0;
 #pragma unroll
           for (int s = 0; s < NS; ++s) prY += P.pr[s] * P.Y[s];
@@ -765,23 +752,21 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
           }
 #pragma unroll
           for (int r = 0; r < NF; ++r) {
-            L[gm.lane(blk, LF_B, cc, r)] = RT(bf[r]);
+            St[st_idx(S, g.N, 1, dw_b(r), p)] = RT(bf[r]);
 #pragma unroll
-            for (int c = 0; c < NF; ++c) L[gm.drow(blk, c, cc, r)] = RT(Df[r][c]);
+            for (int c = 0; c < NF; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Df[r][c]);
           }
           write_push(0, PART_FLOW, R_LAM, R_LVF, w, ca);
         }
         // species part
         {
-          const GroupMap gm = group_map(g.ni, g.nj, part_shape(PART_SPECIES, NS, NT), out.group_cp[1], sizeof(RT));
-          int cc;
-          const long blk = group_blk(gm, i, j, cc);
-          RT *L = reinterpret_cast<RT *>(out.gR[1]);
+          constexpr RecShape S = rec_shape(PART_SPECIES, NS, NT, sizeof(RT));
+          RT *St = reinterpret_cast<RT *>(out.gS[1]);
 #pragma unroll
           for (int r = 0; r < NS; ++r) {
-            L[gm.lane(blk, 0, cc, r)] = RT(-R[r]);
+            St[st_idx(S, g.N, 1, dw_b(r), p)] = RT(-R[r]);
 #pragma unroll
-            for (int c = 0; c < NS; ++c) L[gm.drow(blk, c, cc, r)] = RT(Ai[r][c]);
+            for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
           }
           write_push(1, PART_SPECIES, R_UABS, R_LVC, nullptr, nullptr);
         }

@@ -110,6 +110,23 @@ template <class F> CSI_HD bool newton_bracket(F f, double &x, double lo, double 
   return true;
 }
 
+// Newton iteration from a guess already close to the root (at most 4 steps);
+// false when it has not converged, so that the caller can bracket instead
+template <class F> CSI_HD bool newton_from(F f, double &x) {
+  for (int it = 0; it < 4; ++it) {
+    double fx, dfx;
+    f(x, fx, dfx);
+    if (fx == 0.0) return true;
+    if (!(dfx > 0.0)) return false;
+    const double xn = x - fx / dfx;
+    if (!(xn > 0.0)) return false;
+    const double dx = xn - x;
+    x = xn;
+    if (fabs(dx) <= EPS4 * fabs(x)) return true;
+  }
+  return false;
+}
+
 // Per-cell primitive record
 template <int NS, int NT> struct Prim {
   double rho, u, v, T, Tv, p, c, H, eve, rE;
@@ -124,9 +141,10 @@ template <int NS, int NT> struct Prim {
 };
 
 // q (stored variables) -> primitives and EOS derivatives.  Returns false on a
-// non-physical state.
+// non-physical state.  T0, Tv0 > 0: temperatures already solved for this q
+// (the Newton iterations then start there).
 template <int NS, int NT>
-CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P) {
+CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double T0 = 0.0, double Tv0 = 0.0) {
   double rho = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) { P.rs[s] = q[s]; rho += q[s]; }
@@ -152,8 +170,11 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P) {
         dv += P.rs[s] * (m.cvtr[s] + cvve_s(m, s, T));
       }
     };
-    double T = 1000.0;
-    if (!newton_bracket(f, T, 1.0, 1.0e6)) return false;
+    double T = T0 > 0.0 ? T0 : 1000.0;
+    if (!(T0 > 0.0 && newton_from(f, T))) {
+      T = 1000.0;
+      if (!newton_bracket(f, T, 1.0, 1.0e6)) return false;
+    }
     P.T = T;
     P.Tv = T;
     P.tvT = 1;
@@ -200,7 +221,11 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) { fv += P.rs[s] * eve_s(m, s, t); dv += P.rs[s] * cvve_s(m, s, t); }
       };
-      if (!newton_bracket(f, Tv, 1.0, 1.0e6)) return false;
+      if (Tv0 > 0.0) Tv = Tv0;
+      if (!(Tv0 > 0.0 && newton_from(f, Tv))) {
+        Tv = T;
+        if (!newton_bracket(f, Tv, 1.0, 1.0e6)) return false;
+      }
     }
     P.Tv = Tv;
     P.tvT = has_ve ? 0 : 1;

@@ -55,7 +55,7 @@ inline int nblocks(long n, int b = 256) { return int((n + b - 1) / b); }
 // cells per wave of part q (0: coupled / flow, 1: species) under the group
 // schedule (group_c > 0): 64 / G, the widest strip of G-lane groups
 template <int NS, int NT> inline int group_cells(int group_c, int mode, int q) {
-  const int G = part_shape(q == 1 ? PART_SPECIES : mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT).G;
+  const int G = rec_shape(q == 1 ? PART_SPECIES : mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT, 8).G;
   return group_c > 0 ? 64 / G : 0;
 }
 
@@ -80,9 +80,7 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                   bool stoppable) override {
-    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].R, w.grp[1].R},
-              w.src, w.flags + FL_SING, w.group_c,
-              {group_cells<NS, NT>(w.group_c, mode, 0), group_cells<NS, NT>(w.group_c, mode, 1)},
+    CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].S, w.grp[1].S}, w.src, w.flags + FL_SING, w.group_c,
               w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
@@ -150,10 +148,10 @@ template <int NS, int NT> class Runner : public IRunner {
       for (int q = 0; q < nparts; ++q) {
         const int C = group_cells<NS, NT>(w.group_c, mode, q);
         a.part[q] = GroupPart{w.grp[q], C};
-        const PartShape ps = part_shape(q == 1 ? PART_SPECIES : mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT);
-        const GroupMap m = group_map(g.ni, g.nj, ps, C, sizeof(RT));
+        const int G = rec_shape(q == 1 ? PART_SPECIES : mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT, 8).G;
+        const GroupMap m = group_map(g.ni, g.nj, G);
         nstrip = m.nstrip > nstrip ? m.nstrip : nstrip;
-        const long words = long(m.nstrip) * g.nj * ps.G * long(sizeof(RT)) / 4;
+        const long words = long(m.nstrip) * g.nj * G * long(sizeof(RT)) / 4;
         maxw = words > maxw ? words : maxw;
         rs.tickets[q] = w.grp[q].tickets;
         for (int f = 0; f < 2; ++f) {

@@ -249,10 +249,10 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const Mech *__restrict__ 
   long b0 = 0, b1 = 0;
   int c0 = 0, c1 = 0;
   if (iv.C[0] > 0) {
-    m0 = group_map(g.ni, g.nj, part_shape(mode == 0 ? PART_COUPLED : PART_FLOW, NS, NT), iv.C[0], sizeof(RT));
+    m0 = group_map(g.ni, g.nj, G0);
     b0 = group_blk(m0, i, j, c0);
     if (mode != 0) {
-      m1 = group_map(g.ni, g.nj, part_shape(PART_SPECIES, NS, NT), iv.C[1], sizeof(RT));
+      m1 = group_map(g.ni, g.nj, NS);
       b1 = group_blk(m1, i, j, c1);
     }
   }
