@@ -500,7 +500,8 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     }
     hipError_t e = hipSuccess;
     if (E) e = hipEventRecord(E[0], c->stream);
-    if (e == hipSuccess) e = c->run->prim(c->g, c->w, c->stream, true);
+    // from the second iteration of the call on, the temperature solves start at the previous iteration's
+    if (e == hipSuccess) e = c->run->prim(c->g, c->w, c->stream, true, it > 0);
     if (E && e == hipSuccess) e = hipEventRecord(E[1], c->stream);
     if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[2], c->stream);

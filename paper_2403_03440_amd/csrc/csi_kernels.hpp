@@ -32,11 +32,12 @@ __device__ __forceinline__ int padc(const Geo &g, int i, int j) { return (j + 1)
 // --------------------------------------------------------------- primitives
 // One thread per padded cell: interior cells from Q; ghosts by the boundary
 // conditions (wall mirror, far-field free stream, zero-gradient outflow) or
-// all free stream (bc_mode 1).
+// all free stream (bc_mode 1).  guess: the record still holds the previous
+// iteration's temperatures, where the Newton iterations start.
 template <int NS, int NT>
 __global__ void __launch_bounds__(256) k_prim(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
                                               const double *__restrict__ qfs, double *__restrict__ prim,
-                                              int *__restrict__ bad, const int *__restrict__ done) {
+                                              int *__restrict__ bad, const int *__restrict__ done, int guess) {
   using D = Dims<NS, NT>;
   if (done && *done) return;
   int pc = blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,7 +63,12 @@ __global__ void __launch_bounds__(256) k_prim(Geo g, const Mech *__restrict__ me
     for (int k = 0; k < D::nv; ++k) q[k] = Q[size_t(k) * g.N + c];
   }
   Prim<NS, NT> P;
-  bool ok = prim_from_q<NS, NT>(m, q, P);
+  double T0 = 0.0, Tv0 = 0.0;
+  if (guess) {
+    T0 = prim[size_t(F_T) * g.NP + pc];
+    Tv0 = prim[size_t(F_TV) * g.NP + pc];
+  }
+  bool ok = prim_from_q<NS, NT>(m, q, P, T0, Tv0);
   if (!ok) {
     if (interior && bad) atomicMin(bad, j * g.ni + i);
     return;

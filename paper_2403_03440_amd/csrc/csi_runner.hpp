@@ -32,7 +32,8 @@ class IRunner {
  public:
   virtual ~IRunner() {}
   virtual int nprim() const = 0;
-  virtual hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
+  // guess: start the temperature solves at the previous iteration's temperatures
+  virtual hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable, bool guess = false) = 0;
   virtual hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
   virtual hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                           bool stoppable) = 0;
@@ -63,9 +64,9 @@ template <int NS, int NT> class Runner : public IRunner {
  public:
   int nprim() const override { return PF<NS>::N; }
 
-  hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable) override {
+  hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable, bool guess) override {
     hipLaunchKernelGGL((k_prim<NS, NT>), dim3(nblocks(g.NP)), dim3(256), 0, st, g, w.mech, w.Q, w.qfs, w.prim,
-                       w.flags + FL_BAD, stoppable ? w.flags + FL_DONE : nullptr);
+                       w.flags + FL_BAD, stoppable ? w.flags + FL_DONE : nullptr, guess ? 1 : 0);
     return hipGetLastError();
   }
 
@@ -106,7 +107,7 @@ template <int NS, int NT> class Runner : public IRunner {
   }
 
   hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc) override {
-    hipError_t e = prim(g, w, st, false);
+    hipError_t e = prim(g, w, st, false, false);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_sample<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, xr, jc);
     return hipGetLastError();
