@@ -156,6 +156,7 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(sd.np) * 4,                              // 44 surrogate FP32 parameters
       size_t(2 * sd.n_in + 1) * 8,                    // 45 surrogate scales
       size_t(4) * c->ni * TR_N * 8,                   // 46 sweep trace
+      size_t(2) * N * 8,                              // 47 block diagonals (cell kernel -> block kernel)
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -332,6 +333,7 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.sur.p = reinterpret_cast<const float *>(b + L.off[44]);
   w.sur.scales = reinterpret_cast<const double *>(b + L.off[45]);
   c->trace_buf = reinterpret_cast<long long *>(b + L.off[46]);
+  w.diag = D(47);
   w.trace = c->trace > 0 ? c->trace_buf : nullptr;
   c->has_sur = false;
   w.group_c = c->group_c;

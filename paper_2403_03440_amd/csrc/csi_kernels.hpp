@@ -406,6 +406,11 @@ __device__ __forceinline__ bool invert(double (&a)[N][N], double (&inv)[N][N]) {
 // parts of the implicit operator swept by one wavefront
 enum { PART_COUPLED = 0, PART_FLOW = 2, PART_SPECIES = 3 };
 
+// From this species count on, the diagonal blocks (source Jacobian, block,
+// inverse) are built by k_block with one lane per row; the cell kernel then
+// writes only the scalar diagonals.
+constexpr int BLOCK_NS_MIN = 8;
+
 struct RecShape {
   int G, JVP;   // lanes per cell, whether the push is a flux Jacobian-vector product
   int CW, DW;   // words of the common and of each direction section
@@ -473,6 +478,7 @@ struct CellOut {
   double *src;                 // optional source vector [nv][N] (debug)
   int *bad;
   int group_c;                 // 0: hyperplane schedule (cell-major records); > 0: group schedule
+  double *diag;                // ns >= BLOCK_NS_MIN: [2][N] split dF, dC; coupled dK (for k_block)
   const float *Jsur;           // surrogate J_C [ns * ns][N] (flags bit 4)
   unsigned long long *ddfail;  // count of cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off (stall), use the exact block
@@ -511,8 +517,9 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     // surrogate species block (split form): in 1T the exact J_C is only
     // needed by cells whose surrogate block fails the dominance check; in 2T
     // the flow block's omega_ve row needs the exact derivatives anyway
-    const bool try_sur = do_diag && mode == 1 && (flags & 4) && out.Jsur && *out.surr_off < 0;
-    bool have_jac = do_diag && !(try_sur && NT == 1);
+    constexpr bool BLK = NS >= BLOCK_NS_MIN;
+    const bool try_sur = !BLK && do_diag && mode == 1 && (flags & 4) && out.Jsur && *out.surr_off < 0;
+    bool have_jac = !BLK && do_diag && !(try_sur && NT == 1);
     if (have_jac) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
     else chemistry<NS, NT, false>(m, rs, T, Tv, pp, C);
     double R[NV];
@@ -614,18 +621,22 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
       // coupled: dS_z/dz, z = (rho, m_x, m_y, rhoE, [rhoe_ve], rho_0..rho_{ns-2})
       // storage derivative of omega_s: dw/dq_j = dw_dr + dw_dT dT/dq_j + dw_dTv dTv/dq_j
       double dK = Vdt + 0.5 * slam + svK;
-      double A[NB][NB];
-      {
-        double Jz[NB][NB];
-        coupled_source_jacobian<NS, NT>(P, C, Jz);
+      double Ai[BLK ? 1 : NB][BLK ? 1 : NB];
+      if constexpr (BLK) {
+        out.diag[p] = dK;  // k_block assembles and inverts the block
+      } else {
+        double A[NB][NB];
+        {
+          double Jz[NB][NB];
+          coupled_source_jacobian<NS, NT>(P, C, Jz);
 #pragma unroll
-        for (int r = 0; r < NB; ++r)
+          for (int r = 0; r < NB; ++r)
 #pragma unroll
-          for (int c = 0; c < NB; ++c) A[r][c] = (r == c ? dK : 0.0) - Vp * Jz[r][c];
+            for (int c = 0; c < NB; ++c) A[r][c] = (r == c ? dK : 0.0) - Vp * Jz[r][c];
+        }
+        bool ok = invert<NB>(A, Ai);
+        if (!ok && out.bad) atomicMin(out.bad, p);
       }
-      double Ai[NB][NB];
-      bool ok = invert<NB>(A, Ai);
-      if (!ok && out.bad) atomicMin(out.bad, p);
       double rsum = 0.0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) rsum += R[s];
@@ -641,8 +652,10 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
           bb[long(r) * g.N + p] = RT(bz[r]);
+          if constexpr (!BLK) {
 #pragma unroll
-          for (int c = 0; c < NB; ++c) Dcm[long(r * NB + c) * g.N + p] = RT(Ai[r][c]);
+            for (int c = 0; c < NB; ++c) Dcm[long(r * NB + c) * g.N + p] = RT(Ai[r][c]);
+          }
         }
       } else {
         constexpr RecShape S = rec_shape(PART_COUPLED, NS, NT, sizeof(RT));
@@ -661,8 +674,10 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
           St[st_idx(S, g.N, 1, dw_b(r), p)] = RT(bz[r]);
+          if constexpr (!BLK) {
 #pragma unroll
-          for (int c = 0; c < NB; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
+            for (int c = 0; c < NB; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
+          }
         }
         write_push(0, PART_COUPLED, R_LAM, R_LVK, w, ca);
       }
@@ -673,7 +688,10 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
       double df6[6];
       df6[0] = 1.0 / dF;
       for (int k = 1; k < 6; ++k) df6[k] = 0.0;
-      if (NT == 2) {
+      if (BLK) {
+        out.diag[p] = dF;  // k_block builds both blocks' inverses
+        out.diag[g.N + p] = dC;
+      } else if (NT == 2) {
         double dwv[5];
         flow_source_row<NS, NT>(P, C, dwv);
         // x4 = (r4 + V sum_{j<4} dwv_j x_j) / (dF - V dwv_4)
@@ -682,8 +700,9 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         if (piv == 0.0 && out.bad) atomicMin(out.bad, p);
         df6[5] = 1.0 / piv;
       }
-      double A[NS][NS], Ai[NS][NS];
-      bool use_sur = false, ok = false;
+      double A[BLK ? 1 : NS][BLK ? 1 : NS], Ai[BLK ? 1 : NS][BLK ? 1 : NS];
+      bool use_sur = false, ok = BLK;
+      if constexpr (!BLK) {
       if (try_sur) {
         // surrogate J_C, accepted when D_C = dC I - V J_C is strictly row
         // diagonally dominant with a positive diagonal in molar units
@@ -714,6 +733,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
           for (int c = 0; c < NS; ++c) A[r][c] = (r == c ? dC : 0.0) - Vp * C.dw_dr[r][c];
         ok = invert<NS>(A, Ai);
       }
+      }
       if (!ok && out.bad) atomicMin(out.bad, p);
       double rsum = 0.0;
 #pragma unroll
@@ -725,12 +745,14 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
       bf[3] = -R[NS + 2];
       if (NT == 2) bf[4] = -R[NS + 3];
       if (!grp) {
+        if constexpr (!BLK) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Dcm[long(k) * g.N + p] = RT(df6[k]);
+          for (int k = 0; k < 6; ++k) Dcm[long(k) * g.N + p] = RT(df6[k]);
 #pragma unroll
-        for (int r = 0; r < NS; ++r)
+          for (int r = 0; r < NS; ++r)
 #pragma unroll
-          for (int c = 0; c < NS; ++c) Dcm[long(6 + r * NS + c) * g.N + p] = RT(Ai[r][c]);
+            for (int c = 0; c < NS; ++c) Dcm[long(6 + r * NS + c) * g.N + p] = RT(Ai[r][c]);
+        }
 #pragma unroll
         for (int k = 0; k < NF; ++k) bb[long(k) * g.N + p] = RT(bf[k]);
 #pragma unroll
@@ -759,8 +781,10 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
           for (int r = 0; r < NF; ++r) {
             St[st_idx(S, g.N, 1, dw_b(r), p)] = RT(bf[r]);
+            if constexpr (!BLK) {
 #pragma unroll
-            for (int c = 0; c < NF; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Df[r][c]);
+              for (int c = 0; c < NF; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Df[r][c]);
+            }
           }
           write_push(0, PART_FLOW, R_LAM, R_LVF, w, ca);
         }
@@ -771,8 +795,10 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
 #pragma unroll
           for (int r = 0; r < NS; ++r) {
             St[st_idx(S, g.N, 1, dw_b(r), p)] = RT(-R[r]);
+            if constexpr (!BLK) {
 #pragma unroll
-            for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
+              for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
+            }
           }
           write_push(1, PART_SPECIES, R_UABS, R_LVC, nullptr, nullptr);
         }

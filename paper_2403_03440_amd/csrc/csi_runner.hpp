@@ -2,6 +2,7 @@
 // count and the temperature model; instantiated per species count in
 // csi_inst.hip and dispatched through the IRunner interface.
 #pragma once
+#include "csi_block.hpp"
 #include "csi_group.hpp"
 #include "csi_surrogate.hpp"
 
@@ -15,6 +16,7 @@ struct WS {
   void *b, *dqs, *dq, *Dinv;  // hyperplane schedule: cell-major records and results
   GroupBufs grp[2];           // group schedule: part 0 (coupled / flow), part 1 (species)
   long long *trace;           // optional per-strip sweep trace [fwd, bwd][part][ni][TR_N] (null: off)
+  double *diag;               // [2][N] scalar block diagonals handed from k_cell to k_block
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
   int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels
@@ -82,7 +84,7 @@ template <int NS, int NT> class Runner : public IRunner {
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
                   bool stoppable) override {
     CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].S, w.grp[1].S}, w.src, w.flags + FL_SING, w.group_c,
-              w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
+              w.diag, w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
       hipLaunchKernelGGL((k_cell<NS, NT, double>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
@@ -90,7 +92,29 @@ template <int NS, int NT> class Runner : public IRunner {
     else
       hipLaunchKernelGGL((k_cell<NS, NT, float>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
                          w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    if constexpr (NS >= BLOCK_NS_MIN) {
+      if (flags & 2) {
+        const BlockOut bo{{w.grp[0].S, w.grp[1].S}, w.Dinv, w.group_c, w.diag, w.sur.J, ddfail_counter(w.flags),
+                          w.flags + FL_SURR_OFF, w.flags + FL_SING};
+        if (prec == 0) block<double>(g, w, st, mode, flags, bo, done);
+        else block<float>(g, w, st, mode, flags, bo, done);
+      }
+    }
     return hipGetLastError();
+  }
+
+  // diagonal blocks with one lane per row (ns >= BLOCK_NS_MIN)
+  template <typename RT>
+  void block(const Geo &g, const WS &w, hipStream_t st, int mode, int flags, const BlockOut &bo, const int *done) {
+    if (mode == 0) {
+      constexpr int C = BlockDims<NS, NT, 0>::C;
+      hipLaunchKernelGGL((k_block<NS, NT, RT, 0>), dim3(nblocks(g.N, 2 * C)), dim3(128), 0, st, g, w.mech, w.Q,
+                         w.prim, flags, bo, done);
+    } else {
+      constexpr int C = BlockDims<NS, NT, 1>::C;
+      hipLaunchKernelGGL((k_block<NS, NT, RT, 1>), dim3(nblocks(g.N, 2 * C)), dim3(128), 0, st, g, w.mech, w.Q,
+                         w.prim, flags, bo, done);
+    }
   }
 
   hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable, StallArgs stall) override {
