@@ -156,7 +156,7 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(sd.np) * 4,                              // 44 surrogate FP32 parameters
       size_t(2 * sd.n_in + 1) * 8,                    // 45 surrogate scales
       size_t(4) * c->ni * TR_N * 8,                   // 46 sweep trace
-      size_t(2) * N * 8,                              // 47 block diagonals (cell kernel -> block kernel)
+      size_t(c->ns >= BLOCK_NS_MIN ? hb_fields(c->ns, nv) : 2) * N * 8,  // 47 cell kernel -> block kernel hand-off
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;

@@ -5,143 +5,34 @@
 // for the split parts) is ns x ns (split species part) or nb x nb (coupled).
 // Held by one thread, its FP64 source Jacobian, the block and the inverse do
 // not fit in registers once ns is large.  Here each cell is owned by a group
-// of G lanes and lane k owns row k:
-//   * the chemistry row: lane k accumulates d omega_t / d rho_u (all u) and
-//     d omega_t / dT, dTv of its own species t over all reactions (the
-//     reaction rates are evaluated by every lane of the group);
+// of G lanes, lane k owns row k of the block, and the work of the kinetics is
+// spread over the group instead of repeated by every lane:
+//   * per-cell inputs (X_s, the temperature derivatives, Y_s) come from the
+//     cell kernel and are staged in the group's LDS; lane s evaluates the
+//     Gibbs energy and enthalpy of species s;
+//   * the reactions are taken G at a time, one per lane: the lane evaluates
+//     the rates of its reaction and writes its record (dq_r/d rho_u for every
+//     u, q_r, dq_r/dT, dq_r/dTv) to LDS;
+//   * the lane of species t then adds M_t nu_tr times each record of the
+//     chunk to its row (d omega_t / d rho_u, d omega_t / dT, dTv);
 //   * sums over species (the total-density row of the coupled block, the
-//     vibrational-energy source terms) are column sums through LDS;
+//     vibrational-energy source and its Landau-Teller part, one species per
+//     lane) are group sums through LDS;
 //   * the block row, then a Gauss-Jordan inversion with partial pivoting
-//     across the group: per column the group picks its pivot row (largest
-//     magnitude, lowest lane on ties), the pivot lane publishes its scaled row
-//     in LDS and every other lane eliminates;
+//     across the group through lane reads (no LDS);
 //   * the lane whose row became pivot r writes row r of the inverse.
-// Used for ns >= BLOCK_NS_MIN; the cell kernel writes the right-hand sides, push data
-// and the scalar diagonals (V/dtau + radii) that this kernel reads.
+// Used for ns >= BLOCK_NS_MIN; the cell kernel writes the right-hand sides, push
+// data and the per-cell hand-off that this kernel reads.
 #pragma once
 #include "csi_kernels.hpp"
 
 namespace csi {
 
-// Row t of the species production Jacobian at fixed (T, Tv) (t < 0: none):
-// w = omega_t, row[u] = d omega_t / d rho_u, dT, dTv = d omega_t / dT, dTv.
-// The same kinetics as `chemistry`, accumulated for one species.
-template <int NS, int NT>
-__device__ __forceinline__ void chem_row(const Mech &m, const double *rs, double T, double Tv, double p, int t,
-                                         double &w, double (&row)[NS], double &dT, double &dTv) {
-  double X[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    X[s] = rs[s] / m.M[s];
-    row[s] = 0.0;
-  }
-  w = dT = dTv = 0.0;
-  if (NT == 1) Tv = T;
-  const double lnT = log(T), lnTv = log(Tv);
-  const double Mt = t >= 0 ? m.M[t] : 0.0;
-  const double lnc0 = log(1.0e5 / (RU * T));
-  for (int r = 0; r < m.nr; ++r) {
-    const Reaction &R = m.rx[r];
-    // this species' net stoichiometric coefficient in reaction r
-    double nu = 0.0;
-    for (int e = 0; e < R.nnet; ++e) nu += R.net_s[e] == t ? double(R.net_nu[e]) : 0.0;
-    double lnTf = lnT, dTf_dT = 1.0, dTf_dTv = 0.0, Tf = T;
-    if (NT == 2 && R.tctl == 1) {
-      lnTf = 0.5 * (lnT + lnTv);
-      Tf = exp(lnTf);
-      dTf_dT = 0.5 * Tf / T;
-      dTf_dTv = 0.5 * Tf / Tv;
-    } else if (NT == 2 && R.tctl == 2) {
-      lnTf = lnTv;
-      Tf = Tv;
-      dTf_dT = 0.0;
-      dTf_dTv = 1.0;
-    }
-    const double kf = exp(R.lnA + R.b * lnTf - R.theta / Tf);
-    double lnKc = double(R.dnu) * lnc0, dlnKc = -double(R.dnu) / T;
-    for (int e = 0; e < R.nnet; ++e) {
-      const int s = R.net_s[e];
-      lnKc -= double(R.net_nu[e]) * gRT(m, s, T, lnT);
-      dlnKc += double(R.net_nu[e]) * hRT2(m, s, T);
-    }
-    const double kb = exp(R.lnA + R.b * lnT - R.theta / T - lnKc);
-    double Pf = 1.0, Pb = 1.0;
-    for (int e = 0; e < R.nreac; ++e) Pf *= X[R.reac[e]];
-    for (int e = 0; e < R.nprod; ++e) Pb *= X[R.prod[e]];
-    double Mc = 1.0;
-    if (R.third) {
-      Mc = 0.0;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) Mc += m.eff[r][s] * X[s];
-    }
-    const double net = kf * Pf - kb * Pb;
-    // d q / d X_s, scaled by M_t nu / M_s below
-    double dq[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) dq[s] = R.third ? m.eff[r][s] * net : 0.0;
-    for (int e = 0; e < R.nreac; ++e) {
-      double lo = 1.0;
-      for (int f = 0; f < R.nreac; ++f)
-        if (f != e) lo *= X[R.reac[f]];
-      dq[R.reac[e]] += Mc * kf * lo;
-    }
-    for (int e = 0; e < R.nprod; ++e) {
-      double lo = 1.0;
-      for (int f = 0; f < R.nprod; ++f)
-        if (f != e) lo *= X[R.prod[f]];
-      dq[R.prod[e]] -= Mc * kb * lo;
-    }
-    const double dkf_dTf = kf * (R.b + R.theta / Tf) / Tf;
-    const double dkb_dT = kb * ((R.b + R.theta / T) / T - dlnKc);
-    const double a = Mt * nu;
-    w += a * Mc * net;
-    dT += a * Mc * (dkf_dTf * dTf_dT * Pf - dkb_dT * Pb);
-    dTv += a * Mc * (dkf_dTf * dTf_dTv * Pf);
-#pragma unroll
-    for (int u = 0; u < NS; ++u) row[u] += a * dq[u] / m.M[u];
-  }
-}
-
-// Landau-Teller part of omega_ve (same model as `chemistry`): its value and its
-// derivatives with respect to rho_u, T and Tv.
-template <int NS>
-__device__ __forceinline__ void lt_relax(const Mech &m, const double *rs, double T, double Tv, double p, double &wv,
-                                         double (&dr)[NS], double &dT_, double &dTv_) {
-  const double Tm13 = exp(-log(T) / 3.0);
-  double pT = 0.0, pTv = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (m.kind[s] == ELECTRON) pTv += rs[s] * m.R[s];
-    else pT += rs[s] * m.R[s];
-    dr[s] = 0.0;
-  }
-  wv = dT_ = dTv_ = 0.0;
-  double lt_sum = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    if (m.kind[s] == MOLECULE && m.thv[s] > 0.0) {
-      const double E = exp(18.42 - m.lta[s] * (Tm13 - m.ltb[s]));
-      const double itau = p / ATM * E;
-      const double evT = evib(m.R[s], m.thv[s], T), evTv = evib(m.R[s], m.thv[s], Tv);
-      const double term = rs[s] * (evT - evTv) * itau;
-      wv += term;
-      lt_sum += term;
-      dr[s] += (evT - evTv) * itau;
-      dT_ += rs[s] * cvvib(m.R[s], m.thv[s], T) * itau + term * (m.lta[s] / 3.0) * Tm13 / T;
-      dTv_ += -rs[s] * cvvib(m.R[s], m.thv[s], Tv) * itau;
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < NS; ++s) dr[s] += lt_sum * (m.R[s] * (m.kind[s] == ELECTRON ? Tv : T)) / p;
-  dT_ += lt_sum * pT / p;
-  dTv_ += lt_sum * pTv / p;
-}
-
 struct BlockOut {
   void *gS[2];                 // group schedule: record staging of part 0 (coupled / flow), 1 (species)
   void *Dinv;                  // hyperplane schedule: cell-major inverses (layout as the cell kernel's)
   int group_c;                 // 0: hyperplane schedule; > 0: group schedule
-  const double *diag;          // [2][N] from the cell kernel: split dF, dC; coupled dK
+  const double *hb;            // [hb_fields][N] from the cell kernel
   const float *Jsur;           // surrogate J_C [ns * ns][N]
   unsigned long long *ddfail;  // cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off
@@ -151,16 +42,24 @@ struct BlockOut {
 template <int NS, int NT, int MODE> struct BlockDims {
   static constexpr int NF = NT == 2 ? 5 : 4, NB = NF + NS - 1, NV = NS + 3 + (NT == 2 ? 1 : 0);
   static constexpr int G = MODE == 0 ? NB : NS, C = 64 / G;
-  // LDS per group: column-sum buffer [G][NS], scalars (4G), vector results (2 NS)
-  static constexpr int BUF = G * NS + 4 * G + 2 * NS;
+  static constexpr int RW = NS + 3;   // reaction record: dq/d rho_u (u < NS), q, dq/dT, dq/dTv
+  static constexpr int NSUM = 9;      // scalars summed over the group
+  static constexpr bool SUMS = MODE == 0 || NT == 2;
+  // per-group LDS (doubles): hand-off X | dT/dq | dTv/dq | Y, then g/RT | h/RT^2,
+  // then a scratch area shared by the reaction records and the group sums
+  static constexpr int O_X = 0, O_TQ = NS, O_Y = NS + 2 * NV, O_GH = 2 * NS + 2 * NV, O_S = 4 * NS + 2 * NV;
+  static constexpr int NHB = 2 * NS + 2 * NV;
+  static constexpr int O_SUM = SUMS ? G * NS + NS : 0;  // after the column-sum area [G][NS] and its result [NS]
+  static constexpr int SCR_SUM = SUMS ? O_SUM + NSUM * G + NSUM : 0;
+  static constexpr int SCR = G * RW > SCR_SUM ? G * RW : SCR_SUM;
+  static constexpr int BUF = O_S + SCR;
 };
 
 // Exchange point between the lanes of one wave through LDS: stores made before
 // it are seen by loads after it.  The LDS operations of a wave complete in
 // order; the fences keep the compiler from moving memory operations across it
 // and the (convergent) wave barrier from duplicating or merging the code
-// around it.  Every lane of the wave passes it together (no divergent code
-// between two exchange points communicates).
+// around it.  Every lane of the wave passes it together.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -174,37 +73,41 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
 }
 
-// sum over the group of each lane's vector v[NS]; every lane receives the sums.
-// Lane k < NS sums column k; the lanes beyond repeat column NS - 1 (G <= 2 NS).
+// Sum over the group of each lane's vector v[NS]; every lane receives the sums.
+// `live`: the lane's group owns the buffer (other lanes only read).
 template <int NS, int G>
-__device__ __forceinline__ void group_colsum(double *buf, int k, const double (&v)[NS], double (&s)[NS]) {
-  static_assert(G <= 2 * NS, "column-sum lanes");
+__device__ __forceinline__ void group_colsum(double *scr, int k, bool live, const double (&v)[NS],
+                                             double (&s)[NS]) {
+  double *cs = scr, *res = scr + G * NS;
+  if (live)
 #pragma unroll
-  for (int u = 0; u < NS; ++u) buf[k * NS + u] = v[u];
+    for (int u = 0; u < NS; ++u) cs[k * NS + u] = v[u];
   wave_sync();
   const int kk = k < NS ? k : NS - 1;
   double acc = 0.0;
-  for (int j = 0; j < G; ++j) acc += buf[j * NS + kk];
-  wave_sync();
-  double *res = buf + G * NS + 4 * G;
-  res[kk] = acc;
+  for (int j = 0; j < G; ++j) acc += cs[j * NS + kk];
+  if (live && k < NS) res[k] = acc;
   wave_sync();
 #pragma unroll
   for (int u = 0; u < NS; ++u) s[u] = res[u];
   wave_sync();
 }
-// sums over the group of four scalars per lane; every lane receives them
-template <int NS, int G>
-__device__ __forceinline__ void group_sum4(double *buf, int k, const double (&v)[4], double (&s)[4]) {
-  double *sb = buf + G * NS;
+// sums over the group of N <= G scalars per lane; every lane receives them
+// (lane j < N sums slot j; sb holds [N][G] then the N sums)
+template <int N, int G>
+__device__ __forceinline__ void group_sum(double *sb, int k, bool live, const double (&v)[N], double (&s)[N]) {
+  static_assert(N <= G, "one summing lane per slot");
+  if (live)
 #pragma unroll
-  for (int j = 0; j < 4; ++j) sb[k * 4 + j] = v[j];
+    for (int j = 0; j < N; ++j) sb[j * G + k] = v[j];
+  wave_sync();
+  const int jj = k < N ? k : N - 1;
+  double acc = 0.0;
+  for (int l = 0; l < G; ++l) acc += sb[jj * G + l];
+  if (live && k < N) sb[N * G + k] = acc;
   wave_sync();
 #pragma unroll
-  for (int j = 0; j < 4; ++j) s[j] = 0.0;
-  for (int l = 0; l < G; ++l)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) s[j] += sb[l * 4 + j];
+  for (int j = 0; j < N; ++j) s[j] = sb[N * G + j];
   wave_sync();
 }
 
@@ -220,9 +123,12 @@ __device__ __forceinline__ bool group_invert(int k, int base, double (&A)[G], do
   for (int c = 0; c < G; ++c) Inv[c] = c == k ? 1.0 : 0.0;
   pos = -1;
   bool ok = true;
-#pragma unroll
+#pragma unroll 1
   for (int kc = 0; kc < G; ++kc) {
-    const double a = fabs(A[kc]);
+    double f = 0.0;  // A[kc], picked with constant indices (no dynamically indexed registers)
+#pragma unroll
+    for (int c = 0; c < G; ++c) f = c == kc ? A[c] : f;
+    const double a = fabs(f);
     const double cand = pos >= 0 ? -1.0 : (a >= 0.0 ? a : 0.0);
     int piv = 0;
     double best = -2.0;
@@ -236,7 +142,7 @@ __device__ __forceinline__ bool group_invert(int k, int base, double (&A)[G], do
     if (!(best > 0.0)) ok = false;
     const bool me = k == piv;
     if (me) pos = kc;
-    const double f = A[kc], ip = 1.0 / f;
+    const double ip = 1.0 / f;
     const int src = base + piv;
 #pragma unroll
     for (int c = 0; c < G; ++c) {
@@ -248,89 +154,241 @@ __device__ __forceinline__ bool group_invert(int k, int base, double (&A)[G], do
   return ok;
 }
 
-// One group of G lanes per cell, two waves per block.  MODE 0: coupled block
+// Record of reaction r at (T, Tv) into D[RW] (the same kinetics as
+// `chemistry`): D[u] = (dq_r / dX_u) / M_u (third-body efficiencies and the
+// law-of-mass-action products), D[NS] = q_r, D[NS+1] = dq_r/dT, D[NS+2] =
+// dq_r/dTv, with q_r = M (k_f prod X_reac - k_b prod X_prod).  X, GH: the
+// group's concentrations and g/RT, h/RT^2 per species.
+template <int NS, int NT>
+__device__ __forceinline__ void reaction_record(const Mech &m, int r, double T, double Tv, double lnT, double lnTv,
+                                                double lnc0, const double *X, const double *GH, double *D) {
+  const Reaction &R = m.rx[r];
+  double lnTf = lnT, dTf_dT = 1.0, dTf_dTv = 0.0, Tf = T;
+  if (NT == 2 && R.tctl == 1) {
+    lnTf = 0.5 * (lnT + lnTv);
+    Tf = exp(lnTf);
+    dTf_dT = 0.5 * Tf / T;
+    dTf_dTv = 0.5 * Tf / Tv;
+  } else if (NT == 2 && R.tctl == 2) {
+    lnTf = lnTv;
+    Tf = Tv;
+    dTf_dT = 0.0;
+    dTf_dTv = 1.0;
+  }
+  const double kf = exp(R.lnA + R.b * lnTf - R.theta / Tf);
+  double lnKc = double(R.dnu) * lnc0, dlnKc = -double(R.dnu) / T;
+  for (int e = 0; e < R.nnet; ++e) {
+    const int s = R.net_s[e];
+    lnKc -= double(R.net_nu[e]) * GH[s];
+    dlnKc += double(R.net_nu[e]) * GH[NS + s];
+  }
+  const double kb = exp(R.lnA + R.b * lnT - R.theta / T - lnKc);
+  double Pf = 1.0, Pb = 1.0;
+  for (int e = 0; e < R.nreac; ++e) Pf *= X[R.reac[e]];
+  for (int e = 0; e < R.nprod; ++e) Pb *= X[R.prod[e]];
+  double Mc = 1.0;
+  if (R.third) {
+    Mc = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Mc += m.eff[r][s] * X[s];
+  }
+  const double net = kf * Pf - kb * Pb;
+  if (R.third) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) D[u] = m.eff[r][u] * net * m.iM[u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) D[u] = 0.0;
+  }
+  for (int e = 0; e < R.nreac; ++e) {
+    double lo = 1.0;
+    for (int f = 0; f < R.nreac; ++f)
+      if (f != e) lo *= X[R.reac[f]];
+    const int s = R.reac[e];
+    D[s] += Mc * kf * lo * m.iM[s];
+  }
+  for (int e = 0; e < R.nprod; ++e) {
+    double lo = 1.0;
+    for (int f = 0; f < R.nprod; ++f)
+      if (f != e) lo *= X[R.prod[f]];
+    const int s = R.prod[e];
+    D[s] -= Mc * kb * lo * m.iM[s];
+  }
+  const double dkf_dTf = kf * (R.b + R.theta / Tf) / Tf;
+  const double dkb_dT = kb * ((R.b + R.theta / T) / T - dlnKc);
+  D[NS] = Mc * net;
+  D[NS + 1] = Mc * (dkf_dTf * dTf_dT * Pf - dkb_dT * Pb);
+  D[NS + 2] = Mc * (dkf_dTf * dTf_dTv * Pf);
+}
+
+// One group of G lanes per cell, one wave per block.  MODE 0: coupled block
 // (G = nb; lane 0 carries the last species' chemistry row, which only enters
 // the total-density row; lanes 1..4 have no species row); MODE 1: split
 // species block (G = ns) and the flow block's inverse (lanes k < nf).
 template <int NS, int NT, typename RT, int MODE>
-__global__ void __launch_bounds__(128) k_block(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
-                                               const double *__restrict__ prim, int flags, BlockOut out,
-                                               const int *__restrict__ done) {
+__global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
+                                              const double *__restrict__ prim, int flags, BlockOut out,
+                                              const int *__restrict__ done) {
   using BD = BlockDims<NS, NT, MODE>;
-  constexpr int G = BD::G, C = BD::C, NF = BD::NF, NB = BD::NB, NV = BD::NV;
-  __shared__ double sh[2][C + 1][BD::BUF];
+  constexpr int G = BD::G, C = BD::C, NF = BD::NF, NB = BD::NB, NV = BD::NV, RW = BD::RW;
+  __shared__ double sh[C][BD::BUF];
   if (done && *done) return;
   const Mech &m = *mech;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x;
   const int grp = lane / G, k = lane - grp * G;
-  double *buf = sh[wave][grp < C ? grp : C];  // idle lanes work in a buffer of their own
-  const long cell = (long(blockIdx.x) * 2 + wave) * C + grp;
-  const bool real = grp < C && cell < g.N;
+  const bool live = grp < C;  // lanes past the last group read group 0's buffer and write nothing
+  double *buf = sh[live ? grp : 0];
+  const long cell = long(blockIdx.x) * C + grp;
+  const bool real = live && cell < g.N;
   const int p = int(real ? cell : 0);
   const int i = p % g.ni, j = p / g.ni;
   const int pc = padc(g, i, j);
   const size_t NP = g.NP;
-  double q[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) q[v] = Q[size_t(v) * g.N + p];
-  const double T = prim[F_T * NP + pc], Tv = prim[F_TV * NP + pc], pp = prim[F_P * NP + pc];
-  Prim<NS, NT> P;
-  prim_from_q<NS, NT>(m, q, P, T, Tv);
+  const double T = prim[F_T * NP + pc], Tv = NT == 2 ? prim[F_TV * NP + pc] : T, pp = prim[F_P * NP + pc];
   const double Vp = g.V[p];
+  const double *X = buf + BD::O_X, *TQ = buf + BD::O_TQ, *Ysh = buf + BD::O_Y;
+  double *GH = buf + BD::O_GH, *scr = buf + BD::O_S;
+  // stage the hand-off; lane s evaluates species s's Gibbs energy and enthalpy
+  const double lnT = log(T), lnTv = log(Tv);
+  if (live) {
+    for (int f = k; f < BD::NHB; f += G) buf[f] = out.hb[size_t(HB_X + f) * g.N + p];
+    if (k < NS) {
+      GH[k] = gRT(m, k, T, lnT);
+      GH[NS + k] = hRT2(m, k, T);
+    }
+  }
+  wave_sync();
   // this lane's species row
   const int t = MODE == 0 ? (k >= NF ? k - NF : (k == 0 ? NS - 1 : -1)) : (k < NS ? k : -1);
+  const int tc = t >= 0 ? t : 0;
   double A[G];
+  const double d0 = out.hb[p], d1 = MODE == 1 ? out.hb[size_t(g.N) + p] : 0.0;  // dK | dF, dC
+  // split form: surrogate species block, accepted when the group's block is
+  // strictly row diagonally dominant with a positive diagonal in molar units
+  bool use_sur = false;
+  if (MODE == 1 && (flags & 4) && out.Jsur && *out.surr_off < 0) {
+    double off = 0.0, dkk = 0.0;
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      A[c] = (c == k ? d1 : 0.0) - Vp * double(out.Jsur[size_t(tc * NS + c) * g.N + p]);
+      if (c == k) dkk = A[c];
+      else off += fabs(A[c]) * m.M[c];
+    }
+    const bool dd = dkk > 0.0 && dkk * m.M[tc] > off;
+    const unsigned long long bal = __ballot(dd);
+    constexpr unsigned long long gm = G >= 64 ? ~0ull : (1ull << G) - 1;
+    use_sur = ((bal >> (grp * G)) & gm) == gm;
+    if (!use_sur && k == 0 && real) atomicAdd(out.ddfail, 1ull);
+  }
+  // the exact rows, unless every group of the wave takes the surrogate block
+  // (two temperatures: the flow block needs them anyway)
   double w_t = 0.0, row[NS], dwT = 0.0, dwTv = 0.0;
 #pragma unroll
   for (int u = 0; u < NS; ++u) row[u] = 0.0;
-  // vibrational-energy source terms (two temperatures): d omega_ve / d rho_u, dT, dTv
-  double dwv_dr[NS], dwv_dT = 0.0, dwv_dTv = 0.0;
-  auto ve_terms = [&]() {
-    double wv_lt, dr[NS], dT_, dTv_;
-    lt_relax<NS>(m, q, T, Tv, pp, wv_lt, dr, dT_, dTv_);
-    const double ev = t >= 0 ? eve_s(m, t, Tv) : 0.0, cv = t >= 0 ? cvve_s(m, t, Tv) : 0.0;
+  const bool exact = MODE == 0 || NT == 2 || __ballot(real && !use_sur) != 0ull;
+  if (exact) {
+    const double lnc0 = log(1.0e5 / (RU * T));
+    for (int r0 = 0; r0 < m.nr; r0 += G) {
+      if (live && r0 + k < m.nr) reaction_record<NS, NT>(m, r0 + k, T, Tv, lnT, lnTv, lnc0, X, GH, scr + k * RW);
+      wave_sync();
+      const int nk = m.nr - r0 < G ? m.nr - r0 : G;
+      for (int kk = 0; kk < nk; ++kk) {
+        const double a = t >= 0 ? m.nuM[r0 + kk][tc] : 0.0;
+        if (a != 0.0) {
+          const double *D = scr + kk * RW;
+#pragma unroll
+          for (int u = 0; u < NS; ++u) row[u] += a * D[u];
+          w_t += a * D[NS];
+          dwT += a * D[NS + 1];
+          dwTv += a * D[NS + 2];
+        }
+      }
+      wave_sync();
+    }
+  }
+  // group sums: Landau-Teller terms (species k), pressure derivatives, the
+  // e_ve-weighted production terms and the total-density row's T columns
+  double dwv_dT = 0.0, dwv_dTv = 0.0, Sd0 = 0.0, Sd1 = 0.0, own_dr = 0.0, lt_sum = 0.0;
+  const double ev = NT == 2 && t >= 0 ? eve_s(m, tc, Tv) : 0.0;
+  if (BD::SUMS) {
+    double v[BD::NSUM], S[BD::NSUM];
+#pragma unroll
+    for (int q = 0; q < BD::NSUM; ++q) v[q] = 0.0;
+    if (NT == 2 && k < NS) {
+      const double rs = Q[size_t(k) * g.N + p];
+      if (m.kind[k] == MOLECULE && m.thv[k] > 0.0) {
+        const double Tm13 = exp(-lnT / 3.0);
+        const double itau = pp / ATM * exp(18.42 - m.lta[k] * (Tm13 - m.ltb[k]));
+        const double evT = evib(m.R[k], m.thv[k], T), evTv = evib(m.R[k], m.thv[k], Tv);
+        const double term = rs * (evT - evTv) * itau;
+        own_dr = (evT - evTv) * itau;
+        v[0] = term;
+        v[1] = rs * cvvib(m.R[k], m.thv[k], T) * itau + term * (m.lta[k] / 3.0) * Tm13 / T;
+        v[2] = -rs * cvvib(m.R[k], m.thv[k], Tv) * itau;
+      }
+      const bool el = m.kind[k] == ELECTRON;
+      v[3] = el ? 0.0 : rs * m.R[k];
+      v[4] = el ? rs * m.R[k] : 0.0;
+    }
+    if (NT == 2) {
+      v[5] = dwT * ev;
+      v[6] = dwTv * ev + w_t * (t >= 0 ? cvve_s(m, tc, Tv) : 0.0);
+    }
+    v[7] = dwT;
+    v[8] = dwTv;
+    group_sum<BD::NSUM, G>(scr + BD::O_SUM, k, live, v, S);
+    lt_sum = S[0];
+    dwv_dT = S[1] + lt_sum * S[3] / pp + S[5];
+    dwv_dTv = S[2] + lt_sum * S[4] / pp + S[6];
+    Sd0 = S[7];
+    Sd1 = S[8];
+  }
+  // d omega_ve / d rho_u: the e_ve-weighted species rows, the Landau-Teller
+  // terms of species u and the pressure dependence of the relaxation time
+  double dwv_dr[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) dwv_dr[u] = 0.0;
+  if (NT == 2) {
     double wr[NS];
 #pragma unroll
-    for (int u = 0; u < NS; ++u) wr[u] = row[u] * ev;
-    double cs[NS];
-    group_colsum<NS, G>(buf, k, wr, cs);
+    for (int u = 0; u < NS; ++u) wr[u] = row[u] * ev + (u == k ? own_dr : 0.0);
+    group_colsum<NS, G>(scr, k, live, wr, dwv_dr);
 #pragma unroll
-    for (int u = 0; u < NS; ++u) dwv_dr[u] = dr[u] + cs[u];
-    double sv[4] = {dwT * ev, dwTv * ev + w_t * cv, 0.0, 0.0}, ss[4];
-    group_sum4<NS, G>(buf, k, sv, ss);
-    dwv_dT = dT_ + ss[0];
-    dwv_dTv = dTv_ + ss[1];
-  };
+    for (int u = 0; u < NS; ++u) dwv_dr[u] += lt_sum * (m.R[u] * (m.kind[u] == ELECTRON ? Tv : T)) / pp;
+  }
   bool ok;
   int pos;
   double Inv[G];
   if (MODE == 0) {
-    chem_row<NS, NT>(m, q, T, Tv, pp, t, w_t, row, dwT, dwTv);
-    if (NT == 2) ve_terms();
-    // the total-density row sums every species row
-    double S1[NS], s4[4] = {dwT, dwTv, 0.0, 0.0}, S4[4];
-    group_colsum<NS, G>(buf, k, row, S1);
-    group_sum4<NS, G>(buf, k, s4, S4);
-    // row k of dS/dq (storage columns), then of dS/dz
-    double Jq[NV];
+    // this lane's row of dS/dq (storage columns): a species row, the total
+    // density row (the sum of all species rows) or the vibrational-energy row
+    double rv[NS], vT = dwT, vTv = dwTv;
+    {
+      double S1[NS];
+      group_colsum<NS, G>(scr, k, live, row, S1);
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      double dT, dTv;
-      temp_derivs<NS, NT>(P, c, dT, dTv);
-      double v = 0.0;
-      if (k >= NF) v = (c < NS ? row[c < NS ? c : 0] : 0.0) + dwT * dT + dwTv * dTv;
-      else if (k == 0) v = (c < NS ? S1[c < NS ? c : 0] : 0.0) + S4[0] * dT + S4[1] * dTv;
-      else if (NT == 2 && k == 4) v = (c < NS ? dwv_dr[c < NS ? c : 0] : 0.0) + dwv_dT * dT + dwv_dTv * dTv;
-      Jq[c] = v;
+      for (int u = 0; u < NS; ++u) rv[u] = k >= NF ? row[u] : k == 0 ? S1[u] : 0.0;
     }
-    const double dK = out.diag[p];
+    if (k == 0) {
+      vT = Sd0;
+      vTv = Sd1;
+    } else if (k < NF) {
+      vT = vTv = 0.0;
+    }
+    if (NT == 2 && k == 4) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) rv[u] = dwv_dr[u];
+      vT = dwv_dT;
+      vTv = dwv_dTv;
+    }
+    auto jq = [&](int c) { return (c < NS ? rv[c < NS ? c : 0] : 0.0) + vT * TQ[c] + vTv * TQ[NV + c]; };
+    const double jl = jq(NS - 1);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      const double jz = c == 0 ? Jq[NS - 1] : c < NF ? Jq[NS + c - 1] : Jq[c - NF] - Jq[NS - 1];
-      A[c] = (c == k ? dK : 0.0) - Vp * jz;
+      const double jz = c == 0 ? jl : c < NF ? jq(NS + c - 1) : jq(c - NF) - jl;
+      A[c] = (c == k ? d0 : 0.0) - Vp * jz;
     }
     ok = group_invert<G>(k, grp * G, A, Inv, pos);
-    // row pos of the inverse
     if (real) {
       if (out.group_c > 0) {
         constexpr RecShape S = rec_shape(PART_COUPLED, NS, NT, sizeof(RT));
@@ -344,25 +402,7 @@ __global__ void __launch_bounds__(128) k_block(Geo g, const Mech *__restrict__ m
       }
     }
   } else {
-    const double dF = out.diag[p], dC = out.diag[g.N + p];
-    // surrogate species block, accepted when the group's block is strictly row
-    // diagonally dominant with a positive diagonal in molar units
-    const bool try_sur = (flags & 4) && out.Jsur && *out.surr_off < 0;
-    bool use_sur = false;
-    if (try_sur) {
-      double off = 0.0;
-#pragma unroll
-      for (int c = 0; c < NS; ++c) {
-        A[c] = (c == k ? dC : 0.0) - Vp * double(out.Jsur[size_t(k * NS + c) * g.N + p]);
-        if (c != k) off += fabs(A[c]) * m.M[c];
-      }
-      const bool dd = A[k < NS ? k : 0] > 0.0 && A[k < NS ? k : 0] * m.M[k] > off;
-      const unsigned long long bal = __ballot(dd);
-      constexpr unsigned long long gm = G >= 64 ? ~0ull : (1ull << G) - 1;
-      use_sur = ((bal >> (grp * G)) & gm) == gm;
-      if (!use_sur && k == 0 && real) atomicAdd(out.ddfail, 1ull);
-    }
-    if (!use_sur || NT == 2) chem_row<NS, NT>(m, q, T, Tv, pp, t, w_t, row, dwT, dwTv);
+    const double dF = d0, dC = d1;
     if (!use_sur) {
 #pragma unroll
       for (int c = 0; c < NS; ++c) A[c] = (c == k ? dC : 0.0) - Vp * row[c];
@@ -371,18 +411,13 @@ __global__ void __launch_bounds__(128) k_block(Geo g, const Mech *__restrict__ m
     // -V d omega_ve / d Q_F (frozen Y) eliminated in closed form
     double df6[6] = {1.0 / dF, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (NT == 2) {
-      ve_terms();
       double a0 = 0.0;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) a0 += P.Y[s] * (dwv_dr[s] + dwv_dT * P.dT_dr[s] + dwv_dTv * P.dTv_dr[s]);
+      for (int s = 0; s < NS; ++s) a0 += Ysh[s] * (dwv_dr[s] + dwv_dT * TQ[s] + dwv_dTv * TQ[NV + s]);
       double dwv[5];
       dwv[0] = a0;
 #pragma unroll
-      for (int c = 1; c < 5; ++c) {
-        double dT, dTv;
-        temp_derivs<NS, NT>(P, NS - 1 + c, dT, dTv);
-        dwv[c] = dwv_dT * dT + dwv_dTv * dTv;
-      }
+      for (int c = 1; c < 5; ++c) dwv[c] = dwv_dT * TQ[NS - 1 + c] + dwv_dTv * TQ[NV + NS - 1 + c];
 #pragma unroll
       for (int c = 0; c < 4; ++c) df6[1 + c] = Vp * dwv[c];
       const double piv = dF - Vp * dwv[4];

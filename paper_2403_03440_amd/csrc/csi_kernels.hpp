@@ -408,8 +408,12 @@ enum { PART_COUPLED = 0, PART_FLOW = 2, PART_SPECIES = 3 };
 
 // From this species count on, the diagonal blocks (source Jacobian, block,
 // inverse) are built by k_block with one lane per row; the cell kernel then
-// writes only the scalar diagonals.
+// writes only what that kernel reads per cell (field f of cell p at f N + p):
+// the scalar diagonals (coupled: dK; split: dF, dC), X_s = rho_s / M_s,
+// dT/dq_c and dTv/dq_c over the stored variables, and Y_s.
 constexpr int BLOCK_NS_MIN = 8;
+constexpr int HB_X = 2;
+constexpr int hb_fields(int ns, int nv) { return 2 + 2 * ns + 2 * nv; }
 
 struct RecShape {
   int G, JVP;   // lanes per cell, whether the push is a flux Jacobian-vector product
@@ -478,7 +482,7 @@ struct CellOut {
   double *src;                 // optional source vector [nv][N] (debug)
   int *bad;
   int group_c;                 // 0: hyperplane schedule (cell-major records); > 0: group schedule
-  double *diag;                // ns >= BLOCK_NS_MIN: [2][N] split dF, dC; coupled dK (for k_block)
+  double *diag;                // ns >= BLOCK_NS_MIN: [hb_fields][N] hand-off to k_block
   const float *Jsur;           // surrogate J_C [ns * ns][N] (flags bit 4)
   unsigned long long *ddfail;  // count of cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off (stall), use the exact block
@@ -564,6 +568,21 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     // temperature derivatives w.r.t. stored variables (recomputed from the state)
     Prim<NS, NT> P;
     prim_from_q<NS, NT>(m, q, P, T, Tv);  // T, Tv: k_prim's solution for this q
+    if constexpr (BLK) {
+      double *hb = out.diag + size_t(HB_X) * g.N + p;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        hb[size_t(s) * g.N] = rs[s] / m.M[s];
+        hb[size_t(NS + 2 * NV + s) * g.N] = P.Y[s];
+      }
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double dT, dTv;
+        temp_derivs<NS, NT>(P, c, dT, dTv);
+        hb[size_t(NS + c) * g.N] = dT;
+        hb[size_t(NS + NV + c) * g.N] = dTv;
+      }
+    }
     double Vdt = Vp / dt;
     // hyperplane schedule: cell-major records (field f at f N + p)
     const bool grp = out.group_c > 0;

@@ -22,6 +22,7 @@ inline bool build_mech(const csi_mechanism *mm, Mech &m, std::string &err) {
     m.kind[s] = kd;
     if (kd == ELECTRON) m.e_idx = s;
     m.M[s] = mm->M[s];
+    m.iM[s] = 1.0 / mm->M[s];
     m.R[s] = RU / mm->M[s];
     m.cvtr[s] = kd == ATOM ? 1.5 * m.R[s] : (kd == MOLECULE ? 2.5 * m.R[s] : 0.0);
     m.thv[s] = kd == MOLECULE ? mm->theta_v[s] : 0.0;
@@ -55,6 +56,7 @@ inline bool build_mech(const csi_mechanism *mm, Mech &m, std::string &err) {
         if (R.nprod >= 3) { err = ("more than 3 product molecules"); return false; }
         R.prod[R.nprod++] = s;
       }
+      m.nuM[r_][s] = mm->M[s] * double(nb_ - nf_);
       if (nb_ != nf_) {
         R.net_s[R.nnet] = s;
         R.net_nu[R.nnet] = nb_ - nf_;

@@ -44,6 +44,8 @@ struct Mech {
   Reaction rx[MAXR];
   double eff[MAXR][MAXS];
   double mu_ref, T_ref, mu_exp;
+  double iM[MAXS];          // 1 / M_s
+  double nuM[MAXR][MAXS];   // M_s (nu''_rs - nu'_rs): weight of reaction r's rate in omega_s
 };
 
 template <int NS, int NT> struct Dims {

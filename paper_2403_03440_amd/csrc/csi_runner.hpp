@@ -16,7 +16,7 @@ struct WS {
   void *b, *dqs, *dq, *Dinv;  // hyperplane schedule: cell-major records and results
   GroupBufs grp[2];           // group schedule: part 0 (coupled / flow), part 1 (species)
   long long *trace;           // optional per-strip sweep trace [fwd, bwd][part][ni][TR_N] (null: off)
-  double *diag;               // [2][N] scalar block diagonals handed from k_cell to k_block
+  double *diag;               // [hb_fields][N] per-cell hand-off from k_cell to k_block
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
   int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels
@@ -108,11 +108,11 @@ template <int NS, int NT> class Runner : public IRunner {
   void block(const Geo &g, const WS &w, hipStream_t st, int mode, int flags, const BlockOut &bo, const int *done) {
     if (mode == 0) {
       constexpr int C = BlockDims<NS, NT, 0>::C;
-      hipLaunchKernelGGL((k_block<NS, NT, RT, 0>), dim3(nblocks(g.N, 2 * C)), dim3(128), 0, st, g, w.mech, w.Q,
+      hipLaunchKernelGGL((k_block<NS, NT, RT, 0>), dim3(nblocks(g.N, C)), dim3(64), 0, st, g, w.mech, w.Q,
                          w.prim, flags, bo, done);
     } else {
       constexpr int C = BlockDims<NS, NT, 1>::C;
-      hipLaunchKernelGGL((k_block<NS, NT, RT, 1>), dim3(nblocks(g.N, 2 * C)), dim3(128), 0, st, g, w.mech, w.Q,
+      hipLaunchKernelGGL((k_block<NS, NT, RT, 1>), dim3(nblocks(g.N, C)), dim3(64), 0, st, g, w.mech, w.Q,
                          w.prim, flags, bo, done);
     }
   }
