@@ -163,59 +163,87 @@ template <int NS, int NT>
 __device__ __forceinline__ void reaction_record(const Mech &m, int r, double T, double Tv, double lnT, double lnTv,
                                                 double lnc0, const double *X, const double *GH, double *D) {
   const Reaction &R = m.rx[r];
+  // the reaction's fields and species lists, loaded together (fixed sizes)
+  const double lnA = R.lnA, b = R.b, theta = R.theta;
+  const int tctl = R.tctl, third = R.third, nreac = R.nreac, nprod = R.nprod, nnet = R.nnet, dnu = R.dnu;
+  int rs_[3], ps_[3], es_[6], en_[6];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    rs_[e] = R.reac[e];
+    ps_[e] = R.prod[e];
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    es_[e] = R.net_s[e];
+    en_[e] = R.net_nu[e];
+  }
   double lnTf = lnT, dTf_dT = 1.0, dTf_dTv = 0.0, Tf = T;
-  if (NT == 2 && R.tctl == 1) {
+  if (NT == 2 && tctl == 1) {
     lnTf = 0.5 * (lnT + lnTv);
     Tf = exp(lnTf);
     dTf_dT = 0.5 * Tf / T;
     dTf_dTv = 0.5 * Tf / Tv;
-  } else if (NT == 2 && R.tctl == 2) {
+  } else if (NT == 2 && tctl == 2) {
     lnTf = lnTv;
     Tf = Tv;
     dTf_dT = 0.0;
     dTf_dTv = 1.0;
   }
-  const double kf = exp(R.lnA + R.b * lnTf - R.theta / Tf);
-  double lnKc = double(R.dnu) * lnc0, dlnKc = -double(R.dnu) / T;
-  for (int e = 0; e < R.nnet; ++e) {
-    const int s = R.net_s[e];
-    lnKc -= double(R.net_nu[e]) * GH[s];
-    dlnKc += double(R.net_nu[e]) * GH[NS + s];
+  const double kf = exp(lnA + b * lnTf - theta / Tf);
+  double lnKc = double(dnu) * lnc0, dlnKc = -double(dnu) / T;
+#pragma unroll
+  for (int e = 0; e < 6; ++e)
+    if (e < nnet) {
+      lnKc -= double(en_[e]) * GH[es_[e]];
+      dlnKc += double(en_[e]) * GH[NS + es_[e]];
+    }
+  const double kb = exp(lnA + b * lnT - theta / T - lnKc);
+  double Xr[3], Xp[3], Pf = 1.0, Pb = 1.0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    Xr[e] = e < nreac ? X[rs_[e]] : 1.0;
+    Xp[e] = e < nprod ? X[ps_[e]] : 1.0;
   }
-  const double kb = exp(R.lnA + R.b * lnT - R.theta / T - lnKc);
-  double Pf = 1.0, Pb = 1.0;
-  for (int e = 0; e < R.nreac; ++e) Pf *= X[R.reac[e]];
-  for (int e = 0; e < R.nprod; ++e) Pb *= X[R.prod[e]];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    if (e < nreac) Pf *= Xr[e];
+    if (e < nprod) Pb *= Xp[e];
+  }
   double Mc = 1.0;
-  if (R.third) {
+  if (third) {
     Mc = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) Mc += m.eff[r][s] * X[s];
   }
   const double net = kf * Pf - kb * Pb;
-  if (R.third) {
+  if (third) {
 #pragma unroll
     for (int u = 0; u < NS; ++u) D[u] = m.eff[r][u] * net * m.iM[u];
   } else {
 #pragma unroll
     for (int u = 0; u < NS; ++u) D[u] = 0.0;
   }
-  for (int e = 0; e < R.nreac; ++e) {
-    double lo = 1.0;
-    for (int f = 0; f < R.nreac; ++f)
-      if (f != e) lo *= X[R.reac[f]];
-    const int s = R.reac[e];
-    D[s] += Mc * kf * lo * m.iM[s];
-  }
-  for (int e = 0; e < R.nprod; ++e) {
-    double lo = 1.0;
-    for (int f = 0; f < R.nprod; ++f)
-      if (f != e) lo *= X[R.prod[f]];
-    const int s = R.prod[e];
-    D[s] -= Mc * kb * lo * m.iM[s];
-  }
-  const double dkf_dTf = kf * (R.b + R.theta / Tf) / Tf;
-  const double dkb_dT = kb * ((R.b + R.theta / T) / T - dlnKc);
+  // law-of-mass-action products without factor e (in list order, as a plain product)
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+    if (e < nreac) {
+      double lo = 1.0;
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+        if (f < nreac && f != e) lo *= Xr[f];
+      D[rs_[e]] += Mc * kf * lo * m.iM[rs_[e]];
+    }
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+    if (e < nprod) {
+      double lo = 1.0;
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+        if (f < nprod && f != e) lo *= Xp[f];
+      D[ps_[e]] -= Mc * kb * lo * m.iM[ps_[e]];
+    }
+  const double dkf_dTf = kf * (b + theta / Tf) / Tf;
+  const double dkb_dT = kb * ((b + theta / T) / T - dlnKc);
   D[NS] = Mc * net;
   D[NS + 1] = Mc * (dkf_dTf * dTf_dT * Pf - dkb_dT * Pb);
   D[NS + 2] = Mc * (dkf_dTf * dTf_dTv * Pf);
@@ -270,9 +298,9 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     double off = 0.0, dkk = 0.0;
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
-      A[c] = (c == k ? d1 : 0.0) - Vp * double(out.Jsur[size_t(tc * NS + c) * g.N + p]);
-      if (c == k) dkk = A[c];
-      else off += fabs(A[c]) * m.M[c];
+      const double a = (c == k ? d1 : 0.0) - Vp * double(out.Jsur[size_t(tc * NS + c) * g.N + p]);
+      if (c == k) dkk = a;
+      else off += fabs(a) * m.M[c];
     }
     const bool dd = dkk > 0.0 && dkk * m.M[tc] > off;
     const unsigned long long bal = __ballot(dd);
@@ -292,9 +320,13 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
       if (live && r0 + k < m.nr) reaction_record<NS, NT>(m, r0 + k, T, Tv, lnT, lnTv, lnc0, X, GH, scr + k * RW);
       wave_sync();
       const int nk = m.nr - r0 < G ? m.nr - r0 : G;
-      for (int kk = 0; kk < nk; ++kk) {
-        const double a = t >= 0 ? m.nuM[r0 + kk][tc] : 0.0;
-        if (a != 0.0) {
+      double av[G];  // M_t nu_tr of the chunk's reactions, loaded together
+#pragma unroll
+      for (int kk = 0; kk < G; ++kk) av[kk] = t >= 0 && kk < nk ? m.nuM[r0 + kk][tc] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < G; ++kk) {
+        const double a = av[kk];
+        if (kk < nk && a != 0.0) {
           const double *D = scr + kk * RW;
 #pragma unroll
           for (int u = 0; u < NS; ++u) row[u] += a * D[u];
@@ -403,10 +435,9 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     }
   } else {
     const double dF = d0, dC = d1;
-    if (!use_sur) {
 #pragma unroll
-      for (int c = 0; c < NS; ++c) A[c] = (c == k ? dC : 0.0) - Vp * row[c];
-    }
+    for (int c = 0; c < NS; ++c)
+      A[c] = (c == k ? dC : 0.0) - Vp * (use_sur ? double(out.Jsur[size_t(tc * NS + c) * g.N + p]) : row[c]);
     // flow block: diagonal 1/dF, and in two temperatures the rho e_ve row
     // -V d omega_ve / d Q_F (frozen Y) eliminated in closed form
     double df6[6] = {1.0 / dF, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -424,15 +455,11 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
       if (piv == 0.0 && real && out.bad && k == 0) atomicMin(out.bad, p);
       df6[5] = 1.0 / piv;
     }
-    ok = group_invert<G>(k, grp * G, A, Inv, pos);
+    // the flow block's inverse first (its inputs then end before the inversion)
     if (real) {
       if (out.group_c > 0) {
-        constexpr RecShape S = rec_shape(PART_SPECIES, NS, NT, sizeof(RT));
-        constexpr RecShape SF = rec_shape(PART_FLOW, NS, NT, sizeof(RT));
-        RT *St = reinterpret_cast<RT *>(out.gS[1]);
-#pragma unroll
-        for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, pos, c), p)] = RT(Inv[c]);
         if (k < NF) {
+          constexpr RecShape SF = rec_shape(PART_FLOW, NS, NT, sizeof(RT));
           RT *Sf = reinterpret_cast<RT *>(out.gS[0]);
 #pragma unroll
           for (int c = 0; c < NF; ++c) {
@@ -441,13 +468,23 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
             Sf[st_idx(SF, g.N, 0, rw_d(SF, k, c), p)] = RT(v);
           }
         }
+      } else if (k == 0) {
+        RT *Dcm = reinterpret_cast<RT *>(out.Dinv);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Dcm[long(c) * g.N + p] = RT(df6[c]);
+      }
+    }
+    ok = group_invert<G>(k, grp * G, A, Inv, pos);
+    if (real) {
+      if (out.group_c > 0) {
+        constexpr RecShape S = rec_shape(PART_SPECIES, NS, NT, sizeof(RT));
+        RT *St = reinterpret_cast<RT *>(out.gS[1]);
+#pragma unroll
+        for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, pos, c), p)] = RT(Inv[c]);
       } else {
         RT *Dcm = reinterpret_cast<RT *>(out.Dinv);
 #pragma unroll
         for (int c = 0; c < NS; ++c) Dcm[long(6 + pos * NS + c) * g.N + p] = RT(Inv[c]);
-        if (k == 0)
-#pragma unroll
-          for (int c = 0; c < 6; ++c) Dcm[long(c) * g.N + p] = RT(df6[c]);
       }
     }
   }
