@@ -18,9 +18,10 @@
 //   * sums over species (the total-density row of the coupled block, the
 //     vibrational-energy source and its Landau-Teller part, one species per
 //     lane) are group sums through LDS;
-//   * the block row, then a Gauss-Jordan inversion with partial pivoting
-//     across the group through lane reads (no LDS);
-//   * the lane whose row became pivot r writes row r of the inverse.
+//   * the block row, then an in-place Gauss-Jordan inversion with partial
+//     pivoting across the group (pivot candidates and rows through LDS);
+//   * the lane whose row became pivot r writes row r of the inverse, each
+//     entry to the column of the lane that was pivot at its step.
 // Used for ns >= BLOCK_NS_MIN; the cell kernel writes the right-hand sides, push
 // data and the per-cell hand-off that this kernel reads.
 #pragma once
@@ -51,7 +52,9 @@ template <int NS, int NT, int MODE> struct BlockDims {
   static constexpr int NHB = 2 * NS + 2 * NV;
   static constexpr int O_SUM = SUMS ? G * NS + NS : 0;  // after the column-sum area [G][NS] and its result [NS]
   static constexpr int SCR_SUM = SUMS ? O_SUM + NSUM * G + NSUM : 0;
-  static constexpr int SCR = G * RW > SCR_SUM ? G * RW : SCR_SUM;
+  static constexpr int SCR_INV = G * G + G + (G + 1) / 2;  // rows, candidates, pivot list (ints)
+  static constexpr int SCR0 = G * RW > SCR_SUM ? G * RW : SCR_SUM;
+  static constexpr int SCR = SCR0 > SCR_INV ? SCR0 : SCR_INV;
   static constexpr int BUF = O_S + SCR;
 };
 
@@ -64,13 +67,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-// v as held by lane `src` of the wave (modulo 64; every lane active)
-__device__ __forceinline__ double lane_read(double v, int src) {
-  const long long u = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, int(u & 0xffffffffll));
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, int(u >> 32));
-  return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
 }
 
 // Sum over the group of each lane's vector v[NS]; every lane receives the sums.
@@ -111,16 +107,21 @@ __device__ __forceinline__ void group_sum(double *sb, int k, bool live, const do
   wave_sync();
 }
 
-// Gauss-Jordan inversion with partial pivoting of the G x G matrix whose row k
-// is A (lane base + k); on return Inv holds row `pos` of the inverse.  Per
-// column the group takes as pivot the unused row of largest magnitude (lowest
-// lane on ties; a NaN entry counts as zero) and every lane reads the scaled
-// pivot row from the pivot lane's registers.  Every lane ends with a distinct
-// pos in [0, G); false on a zero pivot (the group agrees).
+// In-place Gauss-Jordan inversion with partial pivoting of the G x G matrix
+// whose row k is A (lane k of the group).  Column kc takes as pivot the unused
+// row of largest magnitude (lowest lane on ties; a NaN entry counts as zero);
+// that lane becomes logical row kc (pos = kc).  With the rows so permuted,
+// B = P A is inverted in place, one column per step: the pivot row is scaled
+// by 1/b_kk (its entry kc becomes 1/b_kk), every other row subtracts its
+// multiple of it (its entry kc becomes -b_ik/b_kk).  On return lane k holds
+// row pos of B^-1 = A^-1 P^T, i.e. A[r] = (A^-1)[pos][piv(r)], where piv(r),
+// the lane chosen at step r, is left in pv[r].  The candidates and each
+// lane's scaled row go through the group's LDS (every lane writes its own
+// slot; the group reads the pivot's), scr: [G][G] rows, [G] candidates.
+// False on a zero pivot (the group agrees).
 template <int G>
-__device__ __forceinline__ bool group_invert(int k, int base, double (&A)[G], double (&Inv)[G], int &pos) {
-#pragma unroll
-  for (int c = 0; c < G; ++c) Inv[c] = c == k ? 1.0 : 0.0;
+__device__ __forceinline__ bool group_invert(double *scr, int *pv, int k, bool live, double (&A)[G], int &pos) {
+  double *rows = scr, *cd = scr + G * G;
   pos = -1;
   bool ok = true;
 #pragma unroll 1
@@ -128,12 +129,17 @@ __device__ __forceinline__ bool group_invert(int k, int base, double (&A)[G], do
     double f = 0.0;  // A[kc], picked with constant indices (no dynamically indexed registers)
 #pragma unroll
     for (int c = 0; c < G; ++c) f = c == kc ? A[c] : f;
-    const double a = fabs(f);
-    const double cand = pos >= 0 ? -1.0 : (a >= 0.0 ? a : 0.0);
+    const double a = fabs(f), ip = 1.0 / f;
+    if (live) {
+      cd[k] = pos >= 0 ? -1.0 : (a >= 0.0 ? a : 0.0);
+#pragma unroll
+      for (int c = 0; c < G; ++c) rows[k * G + c] = c == kc ? ip : A[c] * ip;
+    }
+    wave_sync();
     int piv = 0;
     double best = -2.0;
     for (int j = 0; j < G; ++j) {
-      const double v = lane_read(cand, base + j);
+      const double v = cd[j];
       if (v > best) {
         best = v;
         piv = j;
@@ -142,14 +148,14 @@ __device__ __forceinline__ bool group_invert(int k, int base, double (&A)[G], do
     if (!(best > 0.0)) ok = false;
     const bool me = k == piv;
     if (me) pos = kc;
-    const double ip = 1.0 / f;
-    const int src = base + piv;
+    if (live) pv[kc] = piv;
+    const double *pr = rows + piv * G;
 #pragma unroll
     for (int c = 0; c < G; ++c) {
-      const double ra = lane_read(A[c] * ip, src), ri = lane_read(Inv[c] * ip, src);
-      A[c] = me ? ra : A[c] - f * ra;
-      Inv[c] = me ? ri : Inv[c] - f * ri;
+      const double r = pr[c];
+      A[c] = me ? r : (c == kc ? -f * r : A[c] - f * r);
     }
+    wave_sync();
   }
   return ok;
 }
@@ -390,7 +396,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
   }
   bool ok;
   int pos;
-  double Inv[G];
+  int *pv = reinterpret_cast<int *>(scr + G * G + G);  // pivot lane of each step
   if (MODE == 0) {
     // this lane's row of dS/dq (storage columns): a species row, the total
     // density row (the sum of all species rows) or the vibrational-energy row
@@ -420,17 +426,17 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
       const double jz = c == 0 ? jl : c < NF ? jq(NS + c - 1) : jq(c - NF) - jl;
       A[c] = (c == k ? d0 : 0.0) - Vp * jz;
     }
-    ok = group_invert<G>(k, grp * G, A, Inv, pos);
+    ok = group_invert<G>(scr, pv, k, live, A, pos);
     if (real) {
       if (out.group_c > 0) {
         constexpr RecShape S = rec_shape(PART_COUPLED, NS, NT, sizeof(RT));
         RT *St = reinterpret_cast<RT *>(out.gS[0]);
 #pragma unroll
-        for (int c = 0; c < NB; ++c) St[st_idx(S, g.N, 0, rw_d(S, pos, c), p)] = RT(Inv[c]);
+        for (int r = 0; r < NB; ++r) St[st_idx(S, g.N, 0, rw_d(S, pos, pv[r]), p)] = RT(A[r]);
       } else {
         RT *Dcm = reinterpret_cast<RT *>(out.Dinv);
 #pragma unroll
-        for (int c = 0; c < NB; ++c) Dcm[long(pos * NB + c) * g.N + p] = RT(Inv[c]);
+        for (int r = 0; r < NB; ++r) Dcm[long(pos * NB + pv[r]) * g.N + p] = RT(A[r]);
       }
     }
   } else {
@@ -474,17 +480,17 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
         for (int c = 0; c < 6; ++c) Dcm[long(c) * g.N + p] = RT(df6[c]);
       }
     }
-    ok = group_invert<G>(k, grp * G, A, Inv, pos);
+    ok = group_invert<G>(scr, pv, k, live, A, pos);
     if (real) {
       if (out.group_c > 0) {
         constexpr RecShape S = rec_shape(PART_SPECIES, NS, NT, sizeof(RT));
         RT *St = reinterpret_cast<RT *>(out.gS[1]);
 #pragma unroll
-        for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, pos, c), p)] = RT(Inv[c]);
+        for (int r = 0; r < NS; ++r) St[st_idx(S, g.N, 0, rw_d(S, pos, pv[r]), p)] = RT(A[r]);
       } else {
         RT *Dcm = reinterpret_cast<RT *>(out.Dinv);
 #pragma unroll
-        for (int c = 0; c < NS; ++c) Dcm[long(6 + pos * NS + c) * g.N + p] = RT(Inv[c]);
+        for (int r = 0; r < NS; ++r) Dcm[long(6 + pos * NS + pv[r]) * g.N + p] = RT(A[r]);
       }
     }
   }
