@@ -55,6 +55,7 @@ struct csi_ctx {
   bool has_grid = false, has_mech = false, has_fs = false, bound = false, has_state = false, has_res = false;
   int last_mode = -1, last_prec = -1;
   bool has_dq = false;
+  bool prim_warm = false;  // the prim array holds temperatures solved since set_state (Newton start points)
   // installed surrogate network (inside the workspace)
   bool has_sur = false;
   double sur_ratio = 0.98;
@@ -367,6 +368,7 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   if (rc) return rc;
   c->bound = true;
   c->has_state = false;
+  c->prim_warm = false;
   c->has_res = false;
   return reset_flags(c);
 }
@@ -383,6 +385,7 @@ int csi_set_state(csi_ctx *c, const double *q, int on_device) {
   c->has_state = true;
   c->has_res = false;
   c->has_dq = false;
+  c->prim_warm = false;  // results depend only on the state and the calls since it was set
   c->it_global = 0;
   return reset_flags(c);
 }
@@ -403,7 +406,8 @@ int csi_residual(csi_ctx *c, double cfl, double *norms) {
   if (!(cfl > 0.0)) return c->fail(CSI_ERR_ARG, "cfl must be positive");
   int rc = reset_flags(c);
   if (rc) return rc;
-  hipError_t e = c->run->prim(c->g, c->w, c->stream, false);
+  hipError_t e = c->run->prim(c->g, c->w, c->stream, false, c->prim_warm);
+  c->prim_warm = true;
   if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, false);
   if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, cfl, 0, 0, 1, false);
   if (e == hipSuccess) e = c->run->norms(c->w, c->stream, 0, 0.0, false);
@@ -502,8 +506,9 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     }
     hipError_t e = hipSuccess;
     if (E) e = hipEventRecord(E[0], c->stream);
-    // from the second iteration of the call on, the temperature solves start at the previous iteration's
-    if (e == hipSuccess) e = c->run->prim(c->g, c->w, c->stream, true, it > 0);
+    // the temperature solves start at the previous solve's temperatures once there has been one
+    if (e == hipSuccess) e = c->run->prim(c->g, c->w, c->stream, true, c->prim_warm);
+    c->prim_warm = true;
     if (E && e == hipSuccess) e = hipEventRecord(E[1], c->stream);
     if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[2], c->stream);

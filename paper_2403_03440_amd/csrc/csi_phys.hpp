@@ -91,17 +91,23 @@ CSI_HD double hRT2(const Mech &m, int s, double T) {
   return h;
 }
 
-// Increasing f: Newton steps kept inside a bisection bracket, stop at 4 ulp.
+// Root of an increasing f.  f(x, fv, dv, fa) returns f, f' and the sum of
+// the magnitudes of the terms of f: |f| <= 4 eps fa means f vanishes to its
+// own rounding, and the iteration stops there, as it does on a step of at
+// most 4 ulp of x.
+CSI_HD bool root_reached(double fx, double fa) { return fabs(fx) <= 4.0 * 2.220446049250313e-16 * fa; }
+
+// Newton steps kept inside a bisection bracket.
 template <class F> CSI_HD bool newton_bracket(F f, double &x, double lo, double hi) {
-  double flo, fhi, d;
-  f(lo, flo, d);
-  f(hi, fhi, d);
+  double flo, fhi, d, a;
+  f(lo, flo, d, a);
+  f(hi, fhi, d, a);
   if (!(flo <= 0.0 && fhi >= 0.0)) return false;
   if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
   for (int it = 0; it < 200; ++it) {
-    double fx, dx_;
-    f(x, fx, dx_);
-    if (fx == 0.0) return true;
+    double fx, dx_, fa;
+    f(x, fx, dx_, fa);
+    if (fx == 0.0 || root_reached(fx, fa)) return true;
     if (fx < 0.0) lo = x; else hi = x;
     double xn = x - fx / dx_;
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
@@ -116,9 +122,9 @@ template <class F> CSI_HD bool newton_bracket(F f, double &x, double lo, double 
 // false when it has not converged, so that the caller can bracket instead
 template <class F> CSI_HD bool newton_from(F f, double &x) {
   for (int it = 0; it < 4; ++it) {
-    double fx, dfx;
-    f(x, fx, dfx);
-    if (fx == 0.0) return true;
+    double fx, dfx, fa;
+    f(x, fx, dfx, fa);
+    if (fx == 0.0 || root_reached(fx, fa)) return true;
     if (!(dfx > 0.0)) return false;
     const double xn = x - fx / dfx;
     if (!(xn > 0.0)) return false;
@@ -163,18 +169,21 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
   (void)irho;
   if (NT == 1) {
     double target = P.rE - ekin;
-    auto f = [&](double T, double &fv, double &dv) {
+    auto f = [&](double T, double &fv, double &dv, double &fa) {
       fv = -target;
       dv = 0.0;
+      fa = fabs(target);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        fv += P.rs[s] * (m.cvtr[s] * T + eve_s(m, s, T) + m.hf[s]);
+        const double es = P.rs[s] * (m.cvtr[s] * T + eve_s(m, s, T) + m.hf[s]);
+        fv += es;
+        fa += fabs(es);
         dv += P.rs[s] * (m.cvtr[s] + cvve_s(m, s, T));
       }
     };
     double T = T0 > 0.0 ? T0 : 1000.0;
     if (!(T0 > 0.0 && newton_from(f, T))) {
-      T = 1000.0;
+      T = T0 > 0.0 ? T0 : 1000.0;  // safeguarded iterations from the guess
       if (!newton_bracket(f, T, 1.0, 1.0e6)) return false;
     }
     P.T = T;
@@ -217,15 +226,21 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
       if (P.rs[s] > 0.0 && ((m.kind[s] == MOLECULE && m.thv[s] > 0.0) || m.kind[s] == ELECTRON)) has_ve = true;
     double Tv = T;
     if (has_ve) {
-      auto f = [&](double t, double &fv, double &dv) {
+      auto f = [&](double t, double &fv, double &dv, double &fa) {
         fv = -rEve;
         dv = 0.0;
+        fa = fabs(rEve);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) { fv += P.rs[s] * eve_s(m, s, t); dv += P.rs[s] * cvve_s(m, s, t); }
+        for (int s = 0; s < NS; ++s) {
+          const double es = P.rs[s] * eve_s(m, s, t);
+          fv += es;
+          fa += fabs(es);
+          dv += P.rs[s] * cvve_s(m, s, t);
+        }
       };
       if (Tv0 > 0.0) Tv = Tv0;
       if (!(Tv0 > 0.0 && newton_from(f, Tv))) {
-        Tv = T;
+        Tv = Tv0 > 0.0 ? Tv0 : T;
         if (!newton_bracket(f, Tv, 1.0, 1.0e6)) return false;
       }
     }
