@@ -39,6 +39,10 @@ HEADLINE = "splitmixed_mlp"
 SWEEP_SOURCES = ["csi_group.hpp", "csi_kernels.hpp", "csi_sweep.hpp", "csi_phys.hpp"]
 
 
+MECH_TEXT = {"air5": "5-species air", "air11": "11-species ionised air",
+             "syn20": "seeded 20-species / 60-reaction mechanism"}
+
+
 def nsol(m, mode):
     return m.nb if mode == 0 else m.nf + m.ns
 
@@ -117,11 +121,11 @@ def throughput(csi, I, cfg, m, x, y, fs, variant, steps, warmup, sur=None):
     s = new_solver(csi, I, cfg, m, x, y, fs, sur if jac else None)
     s.set_timing(True)
     if warmup:
-        s.step(mode, kind, cfg.cfl, warmup, precision=prec, jac=jac, cfl_ramp=100, check_every=warmup)
+        s.step(mode, kind, cfg.cfl, warmup, precision=prec, jac=jac, cfl_ramp=cfg.ramp, check_every=warmup)
     s.phase_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = s.step(mode, kind, cfg.cfl, steps, precision=prec, jac=jac, cfl_ramp=100, check_every=steps)
+    st = s.step(mode, kind, cfg.cfl, steps, precision=prec, jac=jac, cfl_ramp=cfg.ramp, check_every=steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ph = s.phase_times()
@@ -145,8 +149,12 @@ def converge(csi, I, cfg, m, x, y, fs, variant, tol, max_iter, sur=None):
     st = None
     fallback, off_at = 0, None
     while done < max_iter:
-        st = s.step(mode, kind, cfg.cfl, min(1000, max_iter - done), precision=prec, jac=jac, cfl_ramp=100,
-                    tol=tol, check_every=50)
+        try:
+            st = s.step(mode, kind, cfg.cfl, min(1000, max_iter - done), precision=prec, jac=jac,
+                        cfl_ramp=cfg.ramp, tol=tol, check_every=50)
+        except csi.CsiError as e:
+            return {"tol": tol, "converged": False, "iters": done, "seconds": time.perf_counter() - t0,
+                    "error": str(e)}
         fallback += st["n_dd_fallback"]
         if st["surrogate_off_at"] >= 0 and off_at is None:
             off_at = st["surrogate_off_at"]
@@ -274,8 +282,9 @@ def main():
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {cfg.ni}x{cfg.nj} polar blunt body, {m.ns}-species air "
-                               f"{'2T' if m.two_temp else '1T'}, CFL {cfg.cfl:g} (ramp over 100 iterations), "
+        "config": {"workload": f"{cfg.name}: {cfg.ni}x{cfg.nj} polar blunt body, {MECH_TEXT[cfg.mech]} "
+                               f"{'2T' if m.two_temp else '1T'}, u {cfg.u_inf:g} m/s, CFL {cfg.cfl:g} "
+                               f"(ramp over {cfg.ramp} iterations), "
                                f"split solver, FP32 sweeps + FP64 residual/chemistry/CC2, species Jacobian block "
                                f"from the BF16 surrogate network with exact fallback, uniform free-stream start",
                    "cells": N},

@@ -398,6 +398,7 @@ class Config:
     seed: int = 3440
     iters: int = 500
     tol: float = 1e-8
+    ramp: int = 100  # iterations over which the CFL number ramps up from 1
 
     def mechanism(self) -> Mechanism:
         if self.mech == "air5":
@@ -428,7 +429,7 @@ CONFIGS = {
     # 512 x 256, 5-species air, two temperatures, CFL 100, to a 1e-8 residual drop
     "c2": Config("c2", 512, 256, "air5", 1, 100.0, 5000.0, iters=20000),
     # 1024 x 512, 11-species ionised air, two temperatures, 7 km/s
-    "c3": Config("c3", 1024, 512, "air11", 1, 100.0, 7000.0, iters=20000),
+    "c3": Config("c3", 1024, 512, "air11", 1, 100.0, 7000.0, iters=20000, ramp=1000),
     # c2 grid and flow with the 11-species mechanism (surrogate workload)
     "c4": Config("c4", 512, 256, "air11", 1, 100.0, 5000.0, iters=20000),
     # 2048 x 1024, seeded 20-species / 60-reaction mechanism, CFL 1000
