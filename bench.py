@@ -165,13 +165,42 @@ def converge(csi, I, cfg, m, x, y, fs, variant, tol, max_iter, sur=None):
             break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    _, qs = s.wall_heat_flux()
+    qw, qs = s.wall_heat_flux()
     out = {"tol": tol, "converged": bool(st["converged"]), "iters": done, "seconds": dt,
-           "drop": st["r_last"] / st["r0"], "q_stag_W_m2": qs}
+           "drop": st["r_last"] / st["r0"], "q_stag_W_m2": qs, "_state": s.get_state(), "_qw": qw}
     if jac:
         out["surrogate_accept_frac"] = 1.0 - fallback / float(cfg.ni * cfg.nj * max(done, 1))
         out["surrogate_off_at"] = off_at
     return out
+
+
+def compare_to_fp64(m, res, ref="split64"):
+    """Each converged variant's state and wall heat flux against the split
+    FP64 run's: per stored variable max|a - b| / max|b| (densities, momenta
+    and energies each scaled by their group's largest magnitude), and the wall
+    heat flux's largest difference over its largest magnitude."""
+    import numpy as np
+    r = res.get(ref, {}).get("to_tol", {})
+    if "_state" not in r:
+        for v in res.values():
+            v.get("to_tol", {}).pop("_state", None)
+            v.get("to_tol", {}).pop("_qw", None)
+        return
+    qb, wb = r["_state"], r["_qw"]
+    ns = m.ns
+    groups = [list(range(ns)), [ns, ns + 1], list(range(ns + 2, qb.shape[0]))]
+    scale = np.abs(qb).max(axis=1)
+    for g in groups:
+        scale[g] = scale[g].max()
+    for v in res.values():
+        t = v.get("to_tol", {})
+        if "_state" in t and t is not r:
+            d = np.abs(t["_state"] - qb).max(axis=1) / np.where(scale > 0, scale, 1.0)
+            t["vs_split64"] = {"per_variable": [float(e) for e in d],
+                               "wall_heat_flux": float(np.abs(t["_qw"] - wb).max() / np.abs(wb).max())}
+    for v in res.values():
+        v.get("to_tol", {}).pop("_state", None)
+        v.get("to_tol", {}).pop("_qw", None)
 
 
 def oracle_threads():
@@ -257,6 +286,7 @@ def main():
     if not args.no_converge:
         for v in names:
             res[v]["to_tol"] = converge(csi, I, cfg, m, x, y, fs, v, args.tol, args.max_iter, sur)
+        compare_to_fp64(m, res)
     if args.copy_probe:
         copy_probe()
     head = res[HEADLINE]

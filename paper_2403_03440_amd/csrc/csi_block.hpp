@@ -88,19 +88,21 @@ __device__ __forceinline__ void group_colsum(double *scr, int k, bool live, cons
   for (int u = 0; u < NS; ++u) s[u] = res[u];
   wave_sync();
 }
-// sums over the group of N <= G scalars per lane; every lane receives them
-// (lane j < N sums slot j; sb holds [N][G] then the N sums)
+// sums over the group of N scalars per lane; every lane receives them
+// (lane k sums slots k, k + G, ...; sb holds [N][G] then the N sums)
 template <int N, int G>
 __device__ __forceinline__ void group_sum(double *sb, int k, bool live, const double (&v)[N], double (&s)[N]) {
-  static_assert(N <= G, "one summing lane per slot");
   if (live)
 #pragma unroll
     for (int j = 0; j < N; ++j) sb[j * G + k] = v[j];
   wave_sync();
-  const int jj = k < N ? k : N - 1;
-  double acc = 0.0;
-  for (int l = 0; l < G; ++l) acc += sb[jj * G + l];
-  if (live && k < N) sb[N * G + k] = acc;
+#pragma unroll
+  for (int q0 = 0; q0 < N; q0 += G) {
+    const int jj = q0 + k < N ? q0 + k : N - 1;
+    double acc = 0.0;
+    for (int l = 0; l < G; ++l) acc += sb[jj * G + l];
+    if (live && q0 + k < N) sb[N * G + q0 + k] = acc;
+  }
   wave_sync();
 #pragma unroll
   for (int j = 0; j < N; ++j) s[j] = sb[N * G + j];

@@ -411,7 +411,7 @@ enum { PART_COUPLED = 0, PART_FLOW = 2, PART_SPECIES = 3 };
 // writes only what that kernel reads per cell (field f of cell p at f N + p):
 // the scalar diagonals (coupled: dK; split: dF, dC), X_s = rho_s / M_s,
 // dT/dq_c and dTv/dq_c over the stored variables, and Y_s.
-constexpr int BLOCK_NS_MIN = 8;
+constexpr int BLOCK_NS_MIN = 5;
 constexpr int HB_X = 2;
 constexpr int hb_fields(int ns, int nv) { return 2 + 2 * ns + 2 * nv; }
 
