@@ -52,7 +52,7 @@ template <int NS, int NT, int MODE> struct BlockDims {
   static constexpr int NHB = 2 * NS + 2 * NV;
   static constexpr int O_SUM = SUMS ? G * NS + NS : 0;  // after the column-sum area [G][NS] and its result [NS]
   static constexpr int SCR_SUM = SUMS ? O_SUM + NSUM * G + NSUM : 0;
-  static constexpr int SCR_INV = G * G + G + (G + 1) / 2;  // rows, candidates, pivot list (ints)
+  static constexpr int SCR_INV = G * G + G;  // rows, then the keys and the pivot list (G ints each)
   static constexpr int SCR0 = G * RW > SCR_SUM ? G * RW : SCR_SUM;
   static constexpr int SCR = SCR0 > SCR_INV ? SCR0 : SCR_INV;
   static constexpr int BUF = O_S + SCR;
@@ -111,51 +111,52 @@ __device__ __forceinline__ void group_sum(double *sb, int k, bool live, const do
 
 // In-place Gauss-Jordan inversion with partial pivoting of the G x G matrix
 // whose row k is A (lane k of the group).  Column kc takes as pivot the unused
-// row of largest magnitude (lowest lane on ties; a NaN entry counts as zero);
-// that lane becomes logical row kc (pos = kc).  With the rows so permuted,
-// B = P A is inverted in place, one column per step: the pivot row is scaled
-// by 1/b_kk (its entry kc becomes 1/b_kk), every other row subtracts its
-// multiple of it (its entry kc becomes -b_ik/b_kk).  On return lane k holds
-// row pos of B^-1 = A^-1 P^T, i.e. A[r] = (A^-1)[pos][piv(r)], where piv(r),
-// the lane chosen at step r, is left in pv[r].  The candidates and each
+// row of largest magnitude; that lane becomes logical row kc (pos = kc).  The
+// candidates are ranked by one 32-bit key per lane: the bits of |a| in FP32
+// with the low 6 bits replaced by 63 - k (so ties, and magnitudes within
+// about 2^-17 of each other, go to the lowest lane; a NaN counts as zero;
+// rows already used rank below every unused one).  With the rows so
+// permuted, B = P A is inverted in place, one column per step: the pivot row
+// is scaled by 1/b_kk (its entry kc becomes 1/b_kk), every other row subtracts
+// its multiple of it (its entry kc becomes -b_ik/b_kk).  On return lane k
+// holds row pos of B^-1 = A^-1 P^T, i.e. A[r] = (A^-1)[pos][piv(r)], where
+// piv(r), the lane chosen at step r, is left in pv[r].  The keys and each
 // lane's scaled row go through the group's LDS (every lane writes its own
-// slot; the group reads the pivot's), scr: [G][G] rows, [G] candidates.
-// False on a zero pivot (the group agrees).
+// slot; the group reads the pivot's), scr: [G][G] rows, then G keys.  False
+// on a zero pivot (the group agrees).
 template <int G>
 __device__ __forceinline__ bool group_invert(double *scr, int *pv, int k, bool live, double (&A)[G], int &pos) {
-  double *rows = scr, *cd = scr + G * G;
+  static_assert(G <= 64, "lane index in 6 bits");
+  double *rows = scr;
+  unsigned *keys = reinterpret_cast<unsigned *>(scr + G * G);
   pos = -1;
   bool ok = true;
-#pragma unroll 1
-  for (int kc = 0; kc < G; ++kc) {
-    double f = 0.0;  // A[kc], picked with constant indices (no dynamically indexed registers)
 #pragma unroll
-    for (int c = 0; c < G; ++c) f = c == kc ? A[c] : f;
-    const double a = fabs(f), ip = 1.0 / f;
+  for (int kc = 0; kc < G; ++kc) {
+    const double f = A[kc], ip = 1.0 / f;
+    const float a = float(fabs(f));
+    const unsigned mag = __float_as_uint(a >= 0.0f ? a : 0.0f) & ~63u;
+    const unsigned key = pos >= 0 ? 0u : ((mag > 64u ? mag : 64u) | unsigned(63 - k));
     if (live) {
-      cd[k] = pos >= 0 ? -1.0 : (a >= 0.0 ? a : 0.0);
+      keys[k] = key;
 #pragma unroll
       for (int c = 0; c < G; ++c) rows[k * G + c] = c == kc ? ip : A[c] * ip;
     }
     wave_sync();
-    int piv = 0;
-    double best = -2.0;
-    for (int j = 0; j < G; ++j) {
-      const double v = cd[j];
-      if (v > best) {
-        best = v;
-        piv = j;
-      }
-    }
-    if (!(best > 0.0)) ok = false;
+    unsigned best = 0u;
+    for (int j = 0; j < G; ++j) best = keys[j] > best ? keys[j] : best;
+    if ((best >> 6) <= 1u) ok = false;  // the pivot is zero (or below FP32's range)
+    const int piv = 63 - int(best & 63u);
     const bool me = k == piv;
     if (me) pos = kc;
     if (live) pv[kc] = piv;
+    // pivot lane: 0 * A + 1 * r; other lanes: A - f r (entry kc: -f r)
+    const double fe = me ? -1.0 : f, sc = me ? 0.0 : 1.0;
     const double *pr = rows + piv * G;
 #pragma unroll
     for (int c = 0; c < G; ++c) {
       const double r = pr[c];
-      A[c] = me ? r : (c == kc ? -f * r : A[c] - f * r);
+      A[c] = c == kc ? -fe * r : fma(-fe, r, A[c] * sc);
     }
     wave_sync();
   }
@@ -398,7 +399,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
   }
   bool ok;
   int pos;
-  int *pv = reinterpret_cast<int *>(scr + G * G + G);  // pivot lane of each step
+  int *pv = reinterpret_cast<int *>(scr + G * G) + G;  // pivot lane of each step (after the keys)
   if (MODE == 0) {
     // this lane's row of dS/dq (storage columns): a species row, the total
     // density row (the sum of all species rows) or the vibrational-energy row
