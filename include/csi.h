@@ -163,6 +163,13 @@ int csi_phase_times(csi_ctx *ctx, double *ms, int reset);
  * free ring slots and the boundary wave's spins on pushes (unused entries are
  * stale). */
 int csi_get_array(csi_ctx *ctx, const char *name, double *out, size_t count);
+/* The arrays "R", "b", "dqs", "dq" and "Dinv" of csi_get_array at the listed
+ * cells only (cells[k] = j * ni + i, 0 <= cells[k] < N): out [F][n_cells]
+ * (host), F as in csi_get_array, element (f, k) at out[f * n_cells + k].  For
+ * checks of full-size runs at sampled cells.  Errors: CSI_ERR_ARG for an unknown
+ * name or a cell out of range; CSI_ERR_STATE before an implicit operator for
+ * the records. */
+int csi_get_cells(csi_ctx *ctx, const char *name, const long long *cells, int n_cells, double *out);
 
 /* ------------------------------------------------------------------------
  * Surrogate of the split species block J_C = d omega_s / d rho_r at fixed T,

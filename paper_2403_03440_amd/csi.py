@@ -28,6 +28,7 @@ _ip = C.POINTER(C.c_int)
 EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_set_mechanism",
             "csi_set_freestream", "csi_workspace_bytes", "csi_bind_workspace", "csi_set_state", "csi_get_state",
             "csi_residual", "csi_implicit_op", "csi_consistency_correct", "csi_step", "csi_wall_heat_flux",
+            "csi_get_cells",
             "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times",
             "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
             "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate"]
@@ -231,6 +232,22 @@ class Solver:
             shape = shapes[name]
         out = np.zeros(shape)
         self._check(self.L.csi_get_array(self.ctx, name.encode(), out.ctypes.data_as(_dp), C.c_size_t(out.size)))
+        return out
+
+    def get_cells(self, name, cells, mode: Optional[int] = None):
+        """`get(name)` at the listed cells only: [F][len(cells)]."""
+        m = self.mech
+        mode = self.last_mode if mode is None else mode
+        if name == "R":
+            F = m.nv
+        elif name == "Dinv":
+            F = m.nb * m.nb if mode == COUPLED else m.nf * m.nf + m.ns * m.ns
+        else:
+            F = self.nsol(mode)
+        cl = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+        out = np.zeros((F, cl.size))
+        self._check(self.L.csi_get_cells(self.ctx, name.encode(), cl.ctypes.data_as(C.POINTER(C.c_longlong)),
+                                         int(cl.size), out.ctypes.data_as(_dp)))
         return out
 
     def initial_state(self, rho_s, u, v, T, Tv):

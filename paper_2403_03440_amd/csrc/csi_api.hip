@@ -720,9 +720,98 @@ int get_records(csi_ctx *c, const std::string &n, double *out, size_t count) {
   return CSI_OK;
 }
 
+// The same arrays for a list of cells, element by element (out [F][n_cells]):
+// full-size runs are checked at sampled cells without copying whole fields.
+int get_cells(csi_ctx *c, const std::string &n, const long long *cells, int nc, double *out) {
+  const size_t N = c->N;
+  auto elem = [&](const void *base, size_t idx, size_t esz, double &v) -> int {
+    if (esz == 8) return hip_check(c, hipMemcpy(&v, static_cast<const char *>(base) + idx * 8, 8, hipMemcpyDeviceToHost), "get");
+    float f = 0.f;
+    const int rc = hip_check(c, hipMemcpy(&f, static_cast<const char *>(base) + idx * 4, 4, hipMemcpyDeviceToHost), "get");
+    v = f;
+    return rc;
+  };
+  if (n == "R") {
+    for (int f = 0; f < c->nv(); ++f)
+      for (int k = 0; k < nc; ++k)
+        if (int rc = elem(c->w.R, size_t(f) * N + size_t(cells[k]), 8, out[size_t(f) * nc + k])) return rc;
+    return CSI_OK;
+  }
+  if (c->last_mode < 0 || c->last_prec < 0) return c->fail(CSI_ERR_STATE, "no implicit operator applied yet");
+  const bool coupled = c->last_mode == CSI_COUPLED;
+  const int nsol = coupled ? c->nb() : c->nsplit();
+  const int nf = c->nf(), ns = c->ns, nb = c->nb();
+  const bool dinv = n == "Dinv";
+  const size_t esz = c->last_prec == CSI_MIXED ? 4 : 8;
+  if (c->group_c == 0) {
+    if (!dinv || coupled) {
+      const void *src = dinv ? c->w.Dinv : n == "b" ? c->w.b : n == "dqs" ? c->w.dqs : c->w.dq;
+      const int F = dinv ? nb * nb : nsol;
+      for (int f = 0; f < F; ++f)
+        for (int k = 0; k < nc; ++k)
+          if (int rc = elem(src, size_t(f) * N + size_t(cells[k]), esz, out[size_t(f) * nc + k])) return rc;
+      return CSI_OK;
+    }
+    // split: the closed-form flow block as a dense inverse, then the species inverse
+    for (int k = 0; k < nc; ++k) {
+      double h6[6];
+      for (int f = 0; f < 6; ++f)
+        if (int rc = elem(c->w.Dinv, size_t(f) * N + size_t(cells[k]), esz, h6[f])) return rc;
+      for (int f = 0; f < nf * nf; ++f) out[size_t(f) * nc + k] = 0.0;
+      for (int r = 0; r < 4; ++r) out[size_t(r * nf + r) * nc + k] = h6[0];
+      if (nf == 5) {
+        for (int q = 0; q < 4; ++q) out[size_t(4 * nf + q) * nc + k] = h6[1 + q] * h6[0] * h6[5];
+        out[size_t(4 * nf + 4) * nc + k] = h6[5];
+      }
+      for (int f = 0; f < ns * ns; ++f)
+        if (int rc = elem(c->w.Dinv, size_t(6 + f) * N + size_t(cells[k]), esz, out[size_t(nf * nf + f) * nc + k]))
+          return rc;
+    }
+    return CSI_OK;
+  }
+  const int nparts = coupled ? 1 : 2;
+  size_t fo = 0;
+  for (int q = 0; q < nparts; ++q) {
+    const RecShape rs = rec_shape(q == 1 ? PART_SPECIES : coupled ? PART_COUPLED : PART_FLOW, ns, c->nt, int(esz));
+    const int G = rs.G;
+    const GroupMap m = group_map(c->ni, c->nj, G);
+    const GroupBufs &gb = c->w.grp[q];
+    const bool res = n == "dq";
+    const int nout = dinv ? G * G : G;
+    for (int k = 0; k < nc; ++k) {
+      const long p = long(cells[k]);
+      const int i = int(p % c->ni), j = int(p / c->ni);
+      int cc;
+      const long blk = group_blk(m, i, j, cc);
+      for (int f = 0; f < nout; ++f) {
+        const int r = dinv ? f / G : f, col = dinv ? f % G : 0;
+        const long idx = dinv ? st_idx(rs, long(N), 0, rw_d(rs, r, col), p)
+                              : n == "b" ? st_idx(rs, long(N), 1, dw_b(r), p)
+                                         : n == "dqs" ? st_idx(rs, long(N), 2, dw_b(r), p) : m.res(blk, cc, r);
+        if (int rc = elem(res ? gb.x : gb.S, size_t(idx), esz, out[(fo + f) * nc + k])) return rc;
+      }
+    }
+    fo += nout;
+  }
+  return CSI_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int csi_get_cells(csi_ctx *c, const char *name, const long long *cells, int n_cells, double *out) {
+  if (!c || !name || !out || n_cells < 0 || (n_cells > 0 && !cells)) return CSI_ERR_ARG;
+  if (!c->bound) return c->fail(CSI_ERR_STATE, "not bound");
+  const std::string n(name);
+  if (n != "R" && n != "b" && n != "dqs" && n != "dq" && n != "Dinv")
+    return c->fail(CSI_ERR_ARG, "get_cells: unknown array " + n);
+  for (int k = 0; k < n_cells; ++k)
+    if (cells[k] < 0 || cells[k] >= (long long)c->N) return c->fail(CSI_ERR_ARG, "get_cells: cell out of range");
+  const int rc = get_cells(c, n, cells, n_cells, out);
+  if (rc) return rc;
+  return hip_check(c, hipStreamSynchronize(c->stream), "get");
+}
 
 int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
   if (!c || !name || !out) return CSI_ERR_ARG;
