@@ -222,7 +222,7 @@ def cpu_baseline(I, cfg, m, x, y, fs, budget_s=20.0):
     t0 = time.perf_counter()
     n = 0
     while True:
-        o.step(1, 2, cfg.cfl, 1, ramp=100, it0=n)
+        o.step(1, 2, cfg.cfl, 1, ramp=cfg.ramp, it0=n)
         n += 1
         if time.perf_counter() - t0 > budget_s or n >= 200:
             break
@@ -325,7 +325,15 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(I, cfg, m, x, y, fs)
+        cb = cpu_baseline(I, cfg, m, x, y, fs)
+        # the oracle follows the split FP64 trajectory: its time to the tolerance
+        # projected from its seconds per iteration and that run's iteration count
+        t64 = res.get("split64", {}).get("to_tol", {})
+        if t64.get("converged"):
+            cb["projected_seconds_to_tol"] = t64["iters"] * N / cb["value"]
+            cb["projection"] = (f"{t64['iters']} iterations (split FP64 run to {args.tol:g}) x the sample's "
+                                f"seconds per iteration")
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 
