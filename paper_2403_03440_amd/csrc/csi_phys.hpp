@@ -75,6 +75,23 @@ CSI_HD double cvve_s(const Mech &m, int s, double Tv) {
   int k = m.kind[s];
   return k == MOLECULE ? cvvib(m.R[s], m.thv[s], Tv) : (k == ELECTRON ? 1.5 * m.R[s] : 0.0);
 }
+// e_ve,s and cv_ve,s together, with one exponential (the same operations as
+// eve_s and cvve_s, so the same values)
+CSI_HD void eve_cvve_s(const Mech &m, int s, double Tv, double &e, double &cv) {
+  const int k = m.kind[s];
+  if (k == MOLECULE && m.thv[s] > 0.0) {
+    const double R = m.R[s], th = m.thv[s];
+    const double x = th / Tv, em = exp(-x), d = 1.0 - em;
+    e = R * th * em / d;
+    cv = R * x * x * em / (d * d);
+  } else if (k == ELECTRON) {
+    e = 1.5 * m.R[s] * Tv;
+    cv = 1.5 * m.R[s];
+  } else {
+    e = 0.0;
+    cv = 0.0;
+  }
+}
 // molar Gibbs energy / (Ru T): hfm/(Ru T) - (gexp ln T + gconst - ln(1 - exp(-thv/T)))
 CSI_HD double gRT(const Mech &m, int s, double T, double lnT) {
   double g = m.hfm[s] / (RU * T) - (m.gexp[s] * lnT + m.gconst[s]);
@@ -175,10 +192,12 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
       fa = fabs(target);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const double es = P.rs[s] * (m.cvtr[s] * T + eve_s(m, s, T) + m.hf[s]);
+        double ev, cv;
+        eve_cvve_s(m, s, T, ev, cv);
+        const double es = P.rs[s] * (m.cvtr[s] * T + ev + m.hf[s]);
         fv += es;
         fa += fabs(es);
-        dv += P.rs[s] * (m.cvtr[s] + cvve_s(m, s, T));
+        dv += P.rs[s] * (m.cvtr[s] + cv);
       }
     };
     double T = T0 > 0.0 ? T0 : 1000.0;
@@ -189,10 +208,12 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
     P.T = T;
     P.Tv = T;
     P.tvT = 1;
-    double rcv = 0.0, rR = 0.0;
+    double rcv = 0.0, rR = 0.0, evs[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      rcv += P.rs[s] * (m.cvtr[s] + cvve_s(m, s, T));
+      double cv;
+      eve_cvve_s(m, s, T, evs[s], cv);
+      rcv += P.rs[s] * (m.cvtr[s] + cv);
       rR += P.rs[s] * m.R[s];
     }
     P.rcv = rcv;
@@ -200,7 +221,7 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
     double beta = rR / rcv;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      double es = m.cvtr[s] * T + eve_s(m, s, T) + m.hf[s];
+      double es = m.cvtr[s] * T + evs[s] + m.hf[s];
       P.dT_dr[s] = (0.5 * k2 - es) / rcv;
       P.pr[s] = m.R[s] * T + rR * P.dT_dr[s];
       P.dTv_dr[s] = P.dT_dr[s];
@@ -232,10 +253,12 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
         fa = fabs(rEve);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const double es = P.rs[s] * eve_s(m, s, t);
+          double ev, cv;
+          eve_cvve_s(m, s, t, ev, cv);
+          const double es = P.rs[s] * ev;
           fv += es;
           fa += fabs(es);
-          dv += P.rs[s] * cvve_s(m, s, t);
+          dv += P.rs[s] * cv;
         }
       };
       if (Tv0 > 0.0) Tv = Tv0;
@@ -246,18 +269,20 @@ CSI_HD bool prim_from_q(const Mech &m, const double *q, Prim<NS, NT> &P, double 
     }
     P.Tv = Tv;
     P.tvT = has_ve ? 0 : 1;
-    double rRh = 0.0, rRe = 0.0, rcvv = 0.0;
+    double rRh = 0.0, rRe = 0.0, rcvv = 0.0, evs[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (m.kind[s] == ELECTRON) rRe += P.rs[s] * m.R[s];
       else rRh += P.rs[s] * m.R[s];
-      rcvv += P.rs[s] * cvve_s(m, s, Tv);
+      double cv;
+      eve_cvve_s(m, s, Tv, evs[s], cv);
+      rcvv += P.rs[s] * cv;
     }
     P.p = rRh * T + rRe * Tv;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       P.dT_dr[s] = (0.5 * k2 - m.cvtr[s] * T - m.hf[s]) / rcv;
-      P.dTv_dr[s] = has_ve ? -eve_s(m, s, Tv) / rcvv : P.dT_dr[s];
+      P.dTv_dr[s] = has_ve ? -evs[s] / rcvv : P.dT_dr[s];
       P.pr[s] = m.R[s] * (m.kind[s] == ELECTRON ? Tv : T) + rRh * P.dT_dr[s] + rRe * P.dTv_dr[s];
     }
     P.dT_dE = 1.0 / rcv;
