@@ -203,6 +203,49 @@ def compare_to_fp64(m, res, ref="split64"):
         v.get("to_tol", {}).pop("_qw", None)
 
 
+def scaling(csi, I, ns_list, steps, warmup):
+    """Implicit-step time against the species count: seeded synthetic species
+    without reactions (non-reacting flow), one temperature, the c2 grid from
+    the uniform free stream.  Per species count and solver: ms per iteration
+    and its phases; the implicit part (cell kernel with the diagonal blocks,
+    both sweeps, update) is fitted to a ns^p."""
+    import numpy as np
+    import torch
+    base = I.CONFIGS["c2"]
+    cfg = I.Config("scaling", base.ni, base.nj, "syn20", 0, base.cfl, base.u_inf)
+    x, y = cfg.grid()
+    rows = []
+    for ns in ns_list:
+        m = I.synthetic(ns, 0, 3442)
+        fs = I.freestream_prims(cfg, m)
+        for v in ("coupled64", "split64", "splitmixed"):
+            mode, kind, prec, _ = VARIANTS[v]
+            s = csi.Solver((x, y), m, fs)
+            s.set_state(s.initial_state(*I.initial_prims(cfg, m)))
+            s.set_timing(True)
+            s.step(mode, kind, cfg.cfl, warmup, precision=prec, cfl_ramp=0, check_every=warmup)
+            s.phase_times(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(mode, kind, cfg.cfl, steps, precision=prec, cfl_ramp=0, check_every=steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ph = {k: p["ms_per_iter"] for k, p in s.phase_times().items() if isinstance(p, dict)}
+            imp = ph["cell"] + ph["sweep_fwd"] + ph["sweep_bwd"] + ph["update"]
+            rows.append({"ns": ns, "variant": v, "ms_per_iter": 1e3 * dt / steps, "implicit_ms": imp, "phases": ph})
+            print(f"# ns {ns} {v}: {1e3 * dt / steps:.3f} ms/it, implicit {imp:.3f} ms", file=sys.stderr, flush=True)
+            del s
+    fit = {}
+    for v in ("coupled64", "split64", "splitmixed"):
+        r = [(q["ns"], q["implicit_ms"]) for q in rows if q["variant"] == v]
+        if len(r) >= 2:
+            fit[v] = float(np.polyfit(np.log([a for a, _ in r]), np.log([b for _, b in r]), 1)[0])
+    return {"metric": "implicit-step time vs species count (non-reacting flow)", "unit": "ms",
+            "config": {"workload": f"{cfg.ni}x{cfg.nj} polar blunt body, seeded synthetic species without "
+                                   f"reactions, 1T, CFL {cfg.cfl:g}, {steps} timed iterations after {warmup}"},
+            "rows": rows, "fitted_exponent_implicit": fit}
+
+
 def oracle_threads():
     n = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS")
@@ -258,6 +301,8 @@ def main():
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--scaling", default="", help="species counts (e.g. 5,11,16,20,32): implicit-step time vs ns "
+                                                 "in non-reacting flow, instead of the workload above")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this implementation runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -267,6 +312,9 @@ def main():
     from paper_2403_03440_amd import csi
     from paper_2403_03440_amd import inputs as I
 
+    if args.scaling:
+        print(json.dumps(scaling(csi, I, [int(v) for v in args.scaling.split(",")], args.steps, args.warmup)))
+        return
     cfg = I.CONFIGS[args.config]
     m = cfg.mechanism()
     x, y = cfg.grid()

@@ -99,6 +99,8 @@ const char *csi_last_error(const csi_ctx *ctx);
  * free stream on all four sides. */
 int csi_set_grid(csi_ctx *ctx, int ni, int nj, const double *x_nodes, const double *y_nodes, double T_wall,
                  int bc_mode);
+/* Compiled species counts: 2, 3, 5 and 11 (one and two temperatures), 16, 20
+ * and 32 (one temperature); others return CSI_ERR_UNSUPPORTED. */
 int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
 /* free stream from primitives (rho_s [ns] host, u, v, T, Tv) */
 int csi_set_freestream(csi_ctx *ctx, const double *rho_s, double u, double v, double T, double Tv);

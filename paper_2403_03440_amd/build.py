@@ -10,9 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsi.so")
-SPECIES = tuple(int(s) for s in os.environ.get("CSI_SPECIES", "2,3,5,11,20").split(","))
-# temperature models compiled per species count (the seeded 20-species mechanism is one-temperature)
-MODELS = {20: (1,)}
+SPECIES = tuple(int(s) for s in os.environ.get("CSI_SPECIES", "2,3,5,11,16,20,32").split(","))
+# temperature models compiled per species count (the seeded synthetic mechanisms are one-temperature)
+MODELS = {16: (1,), 20: (1,), 32: (1,)}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I" + CSRC, "-Wno-unused-result"]

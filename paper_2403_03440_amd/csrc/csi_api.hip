@@ -15,11 +15,12 @@
 using namespace csi;
 
 // per-(species count, temperature model) factories; weak, so that a build may
-// compile a subset (the 20-species mechanism is built for one temperature)
+// compile a subset (the 16-, 20- and 32-species mechanisms are built for one temperature)
 #define CSI_WEAK_FACTORY(ns, nt) __attribute__((weak)) csi::IRunner *csi_make_runner_##ns##_##nt();
 CSI_WEAK_FACTORY(2, 1) CSI_WEAK_FACTORY(2, 2) CSI_WEAK_FACTORY(3, 1) CSI_WEAK_FACTORY(3, 2)
 CSI_WEAK_FACTORY(5, 1) CSI_WEAK_FACTORY(5, 2) CSI_WEAK_FACTORY(11, 1) CSI_WEAK_FACTORY(11, 2)
-CSI_WEAK_FACTORY(20, 1) CSI_WEAK_FACTORY(20, 2)
+CSI_WEAK_FACTORY(16, 1) CSI_WEAK_FACTORY(16, 2) CSI_WEAK_FACTORY(20, 1) CSI_WEAK_FACTORY(20, 2)
+CSI_WEAK_FACTORY(32, 1) CSI_WEAK_FACTORY(32, 2)
 
 namespace csi {
 IRunner *make_runner(int ns, int nt) {
@@ -32,7 +33,9 @@ IRunner *make_runner(int ns, int nt) {
     CSI_PICK(3)
     CSI_PICK(5)
     CSI_PICK(11)
+    CSI_PICK(16)
     CSI_PICK(20)
+    CSI_PICK(32)
     default: return nullptr;
   }
 #undef CSI_PICK
