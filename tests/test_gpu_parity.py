@@ -22,7 +22,7 @@ def _csi():
 
 # physical states: the oracle's own iterations from the free stream
 EVOLVED = [("air5_1T", 32, 24), ("air5_2T", 32, 24), ("air11_2T", 32, 24), ("syn20_1T", 32, 24),
-           ("toy2_1T", 24, 16)]
+           ("toy2_1T", 24, 16), ("syn16_1T", 20, 12), ("syn32_1T", 13, 9)]
 # seeded random states (milder temperatures, mildly reacting) for a two-temperature toy
 RANDOM = [("toy3_2T", 7, 5)]
 CASES = [(n, a, b, "evolved") for n, a, b in EVOLVED] + [(n, a, b, "random") for n, a, b in RANDOM]
