@@ -212,7 +212,7 @@ def scaling(csi, I, ns_list, steps, warmup):
     import numpy as np
     import torch
     base = I.CONFIGS["c2"]
-    cfg = I.Config("scaling", base.ni, base.nj, "syn20", 0, base.cfl, base.u_inf)
+    cfg = I.Config("scaling", base.ni, base.nj, "syn20", 0, 10.0, base.u_inf)
     x, y = cfg.grid()
     rows = []
     for ns in ns_list:
@@ -223,11 +223,11 @@ def scaling(csi, I, ns_list, steps, warmup):
             s = csi.Solver((x, y), m, fs)
             s.set_state(s.initial_state(*I.initial_prims(cfg, m)))
             s.set_timing(True)
-            s.step(mode, kind, cfg.cfl, warmup, precision=prec, cfl_ramp=0, check_every=warmup)
+            s.step(mode, kind, cfg.cfl, warmup, precision=prec, cfl_ramp=cfg.ramp, check_every=warmup)
             s.phase_times(reset=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.step(mode, kind, cfg.cfl, steps, precision=prec, cfl_ramp=0, check_every=steps)
+            s.step(mode, kind, cfg.cfl, steps, precision=prec, cfl_ramp=cfg.ramp, check_every=steps)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ph = {k: p["ms_per_iter"] for k, p in s.phase_times().items() if isinstance(p, dict)}
@@ -242,7 +242,8 @@ def scaling(csi, I, ns_list, steps, warmup):
             fit[v] = float(np.polyfit(np.log([a for a, _ in r]), np.log([b for _, b in r]), 1)[0])
     return {"metric": "implicit-step time vs species count (non-reacting flow)", "unit": "ms",
             "config": {"workload": f"{cfg.ni}x{cfg.nj} polar blunt body, seeded synthetic species without "
-                                   f"reactions, 1T, CFL {cfg.cfl:g}, {steps} timed iterations after {warmup}"},
+                                   f"reactions, 1T, CFL ramp to {cfg.cfl:g} over {cfg.ramp} iterations, "
+                                   f"{steps} timed iterations after {warmup}"},
             "rows": rows, "fitted_exponent_implicit": fit}
 
 
