@@ -86,7 +86,10 @@ typedef struct {
   int bad_cell;    /* first non-physical cell, or -1 */
   double r0, r_last;
   long long n_dd_fallback; /* cell-iterations whose surrogate block failed the dominance check (exact used) */
-  int surrogate_off_at;    /* iteration at which the stall policy switched the surrogate off, or -1 */
+  int surrogate_off_at;    /* iteration from which the surrogate was switched off (stall policy or
+                              divergence fallback), or -1 */
+  int surrogate_diverged;  /* 1 if iterations with the surrogate ended in a non-physical state or a zero
+                              pivot and the call restarted from its first state with the exact block */
 } csi_step_stats;
 
 int csi_create(csi_ctx **ctx, int device, void *hip_stream);
@@ -125,7 +128,13 @@ int csi_residual(csi_ctx *ctx, double cfl, double *norms);
 int csi_implicit_op(csi_ctx *ctx, int mode, int precision, int jac);
 /* closure (coupled) or CC1 / CC2 (split) and the FP64 update of Q (paper Section 2.3) */
 int csi_consistency_correct(csi_ctx *ctx, int kind);
-/* iterate: residual -> implicit_op -> consistency_correct, with a CFL ramp and stop test */
+/* iterate: residual -> implicit_op -> consistency_correct, with a CFL ramp and stop test.
+ * With CSI_JAC_SURROGATE the state at the start of the call is kept in the
+ * workspace: if iterations with the surrogate on end in a non-physical state or
+ * a zero pivot, the call restarts from it with the exact block (surrogate
+ * switched off from the call's first iteration; stats surrogate_diverged), once
+ * per call.  Without the surrogate, or after that, such iterations return
+ * CSI_ERR_NONFINITE / CSI_ERR_SINGULAR. */
 int csi_step(csi_ctx *ctx, const csi_step_params *p, csi_step_stats *s);
 /* wall heat flux into the wall per wall cell (host [ni]) and its value at the stagnation line */
 int csi_wall_heat_flux(csi_ctx *ctx, double *qw, double *q_stag);

@@ -58,7 +58,7 @@ class StepParams(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("it_conv", C.c_int), ("n_clipped", C.c_int),
                 ("bad_cell", C.c_int), ("r0", C.c_double), ("r_last", C.c_double),
-                ("n_dd_fallback", C.c_longlong), ("surrogate_off_at", C.c_int)]
+                ("n_dd_fallback", C.c_longlong), ("surrogate_off_at", C.c_int), ("surrogate_diverged", C.c_int)]
 
 
 class MlpBatch(C.Structure):

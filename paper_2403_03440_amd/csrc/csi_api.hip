@@ -161,6 +161,7 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(2 * sd.n_in + 1) * 8,                    // 45 surrogate scales
       size_t(4) * c->ni * TR_N * 8,                   // 46 sweep trace
       size_t(c->ns >= BLOCK_NS_MIN ? hb_fields(c->ns, nv) : 2) * N * 8,  // 47 cell kernel -> block kernel hand-off
+      size_t(nv) * N * 8,                             // 48 state at the start of csi_step (surrogate divergence fallback)
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -338,6 +339,7 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.sur.scales = reinterpret_cast<const double *>(b + L.off[45]);
   c->trace_buf = reinterpret_cast<long long *>(b + L.off[46]);
   w.diag = D(47);
+  w.qbak = D(48);
   w.trace = c->trace > 0 ? c->trace_buf : nullptr;
   c->has_sur = false;
   w.group_c = c->group_c;
@@ -493,6 +495,19 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   st.surrogate_off_at = -1;
   int fl[FL_N];
   const long it_start = c->it_global;
+  // Divergence fallback of the surrogate: the state at the start of the call.
+  // If iterations with the surrogate on end in a non-physical state or a zero
+  // pivot, that state is restored, the surrogate is switched off from the
+  // call's first iteration on, and the iterations are repeated with the exact
+  // block (once per call).  A state from a later clean check is not kept: the
+  // blocks of a wrong network can spoil the state before any flag shows it.
+  const size_t qbytes = size_t(c->nv()) * c->N * 8;
+  bool guard = sur;
+  const long bak_global = c->it_global;
+  const int bak_it = 0;
+  if (guard && (rc = hip_check(c, hipMemcpyAsync(c->w.qbak, c->w.Q, qbytes, hipMemcpyDeviceToDevice, c->stream),
+                               "state copy")))
+    return rc;
   for (int it = 0; it < p->max_iter; ++it) {
     long m = c->it_global;
     double cfl = p->cfl_ramp > 0 ? std::pow(p->cfl, double(std::min<long>(m, p->cfl_ramp)) / p->cfl_ramp) : p->cfl;
@@ -544,6 +559,21 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
       if (fl[FL_ABORT]) {
         if (s) *s = st;
         return c->fail(CSI_ERR_HIP, "step: a sweep wave timed out waiting for its neighbour strip");
+      }
+      if ((fl[FL_BAD] != INT_MAX || fl[FL_SING] != INT_MAX) && guard && fl[FL_SURR_OFF] < 0 && !fl[FL_ABORT]) {
+        const int clean[1] = {INT_MAX};
+        const int off = int(bak_global);
+        hipError_t e2 = hipMemcpyAsync(c->w.Q, c->w.qbak, qbytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e2 == hipSuccess) e2 = hipMemcpyAsync(c->w.flags + FL_BAD, clean, sizeof(int), hipMemcpyHostToDevice, c->stream);
+        if (e2 == hipSuccess) e2 = hipMemcpyAsync(c->w.flags + FL_SING, clean, sizeof(int), hipMemcpyHostToDevice, c->stream);
+        if (e2 == hipSuccess) e2 = hipMemcpyAsync(c->w.flags + FL_SURR_OFF, &off, sizeof(int), hipMemcpyHostToDevice, c->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+        if ((rc = hip_check(c, e2, "divergence fallback"))) return rc;
+        c->it_global = bak_global;
+        it = bak_it - 1;
+        st.surrogate_diverged = 1;
+        guard = false;
+        continue;
       }
       if (fl[FL_BAD] != INT_MAX || fl[FL_SING] != INT_MAX) {
         st.bad_cell = fl[FL_BAD] != INT_MAX ? fl[FL_BAD] : fl[FL_SING];

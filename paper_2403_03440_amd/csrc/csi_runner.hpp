@@ -17,6 +17,7 @@ struct WS {
   GroupBufs grp[2];           // group schedule: part 0 (coupled / flow), part 1 (species)
   long long *trace;           // optional per-strip sweep trace [fwd, bwd][part][ni][TR_N] (null: off)
   double *diag;               // [hb_fields][N] per-cell hand-off from k_cell to k_block
+  double *qbak;               // [nv][N] state at the start of csi_step (surrogate divergence fallback)
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
   int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels

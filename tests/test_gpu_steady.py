@@ -93,3 +93,37 @@ def test_steady_state_matches_oracle(mech, u, with_sur):
         s.residual(cfg.cfl)
         qw, qs = s.wall_heat_flux()
         _compare("split mixed + surrogate vs oracle", m, s.get_state(), qw, qs, qo, qwo, qso)
+
+
+def test_surrogate_divergence_fallback():
+    """A network trained with too few optimiser steps (240 Adam steps on the
+    24 x 16 case) yields blocks that pass the dominance check yet drive the
+    split iteration to a non-physical state within about 20 iterations.  The
+    step then restores the state it started from, switches the surrogate off
+    and repeats the iterations with the exact block: the run converges,
+    reports the fallback, and reaches the oracle's steady state."""
+    from paper_2403_03440_amd import csi
+    from paper_2403_03440_amd import surrogate as S
+    cfg = I.Config("steady", 24, 16, "air5", 1, 10.0, 5000.0)
+    m = cfg.mechanism()
+    x, y = cfg.grid()
+    fs = I.freestream_prims(cfg, m)
+    s = csi.Solver((x, y), m, fs)
+    q0 = s.initial_state(*I.initial_prims(cfg, m))
+    qo, qwo, qso = _oracle_steady(cfg, m, x, y, fs, q0)
+    s.set_state(q0)
+    xr, jc, _ = S.collect(s, (csi.SPLIT, csi.CC2, csi.MIXED), cfg.cfl, 16 * s.N, every=30)
+    params, scales, hist = S.train(xr, jc, epochs=20, batch=512, lr=3e-3, seed=5)
+    print(f"under-trained network: loss {hist[0][2]:.3g} -> {hist[-1][2]:.3g}", flush=True)
+    s.set_state(q0)
+    s.set_surrogate(params, scales)
+    st = s.step(csi.SPLIT, csi.CC2, cfg.cfl, 8000, precision=csi.MIXED, jac=csi.JAC_SURROGATE,
+                cfl_ramp=cfg.ramp, tol=TOL_DROP, check_every=10)
+    print(f"iterations {st['iters']}, converged {st['converged']}, diverged {st['surrogate_diverged']}, "
+          f"surrogate off from {st['surrogate_off_at']}", flush=True)
+    assert st["surrogate_diverged"] == 1
+    assert st["surrogate_off_at"] >= 0
+    assert st["converged"]
+    s.residual(cfg.cfl)
+    qw, qs = s.wall_heat_flux()
+    _compare("after the fallback vs oracle", m, s.get_state(), qw, qs, qo, qwo, qso)
