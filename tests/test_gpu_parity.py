@@ -221,6 +221,15 @@ def test_error_paths():
     with pytest.raises(csi.CsiError) as e:
         s.consistency_correct(2)  # coupled mode takes the closure
     assert e.value.code == -1
+    # sampled reads: same values as the full arrays, bad names and cells rejected
+    cells = [0, 7, 23]
+    assert np.array_equal(s.get_cells("R", cells), s.get("R")[:, cells])
+    assert np.array_equal(s.get_cells("Dinv", cells, 0), s.get("Dinv", 0)[:, cells])
+    assert np.array_equal(s.get_cells("b", cells, 0), s.get("b", 0)[:, cells])
+    for name, cl in (("R", [24]), ("R", [-1]), ("Q", [0])):
+        with pytest.raises(csi.CsiError) as e:
+            s.get_cells(name, cl)
+        assert e.value.code == -1
     bad = q0.copy()
     bad[0, 5] = -1.0  # negative density in one cell
     bad[1:m.ns, 5] = 0.0
