@@ -271,9 +271,23 @@ def cpu_baseline(I, cfg, m, x, y, fs, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s or n >= 200:
             break
     dt = time.perf_counter() - t0
-    return {"value": cfg.ni * cfg.nj * n / dt, "unit": "cell-iters/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} split-CC2 FP64 iterations of the {cfg.ni}x{cfg.nj} workload from the free "
-                      f"stream ({dt:.1f} s, {threads} OpenMP threads)"}
+    out = {"value": cfg.ni * cfg.nj * n / dt, "unit": "cell-iters/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n} split-CC2 FP64 iterations of the {cfg.ni}x{cfg.nj} workload from the free "
+                     f"stream ({dt:.1f} s, {threads} OpenMP threads)"}
+    # the same iterations on one thread (a shorter sample)
+    o1 = orc.setup((x, y), m, fs, threads=1)
+    o1.set_state(o1.prim_to_cons(*I.initial_prims(cfg, m)))
+    t0 = time.perf_counter()
+    n1 = 0
+    while True:
+        o1.step(1, 2, cfg.cfl, 1, ramp=cfg.ramp, it0=n1)
+        n1 += 1
+        if time.perf_counter() - t0 > budget_s / 2 or n1 >= 50:
+            break
+    dt1 = time.perf_counter() - t0
+    out["value_1_thread"] = cfg.ni * cfg.nj * n1 / dt1
+    out["sample_1_thread"] = f"first {n1} of the same iterations on 1 thread ({dt1:.1f} s)"
+    return out
 
 
 def copy_probe(gib=1.0, reps=3):
