@@ -47,14 +47,19 @@ template <int NS, int NT, int MODE> struct BlockDims {
   static constexpr int NSUM = 9;      // scalars summed over the group
   static constexpr bool SUMS = MODE == 0 || NT == 2;
   // per-group LDS (doubles): hand-off X | dT/dq | dTv/dq | Y, then g/RT | h/RT^2,
-  // then a scratch area shared by the reaction records and the group sums
+  // then a scratch area
   static constexpr int O_X = 0, O_TQ = NS, O_Y = NS + 2 * NV, O_GH = 2 * NS + 2 * NV, O_S = 4 * NS + 2 * NV;
   static constexpr int NHB = 2 * NS + 2 * NV;
-  static constexpr int O_SUM = SUMS ? G * NS + NS : 0;  // after the column-sum area [G][NS] and its result [NS]
-  static constexpr int SCR_SUM = SUMS ? O_SUM + NSUM * G + NSUM : 0;
-  static constexpr int SCR_INV = G * G + G;  // rows, then the keys and the pivot list (G ints each)
+  // the scratch area holds, one after the other (wave syncs between them):
+  // the chunk's reaction records [G][RW], the scalar sums [NSUM][G] + NSUM,
+  // the column sums [G][NS] + NS, the inversion's rows [G][G] + keys/pivots
+  static constexpr int O_SUM = 0;
+  static constexpr int SCR_SUM = SUMS ? NSUM * G + NSUM : 0;
+  static constexpr int SCR_CS = SUMS ? G * NS + NS : 0;
+  static constexpr int SCR_INV = G * G + G;
   static constexpr int SCR0 = G * RW > SCR_SUM ? G * RW : SCR_SUM;
-  static constexpr int SCR = SCR0 > SCR_INV ? SCR0 : SCR_INV;
+  static constexpr int SCR1 = SCR_CS > SCR_INV ? SCR_CS : SCR_INV;
+  static constexpr int SCR = SCR0 > SCR1 ? SCR0 : SCR1;
   static constexpr int BUF = O_S + SCR;
 };
 
