@@ -45,6 +45,10 @@ IRunner *make_runner(int ns, int nt) {
 struct csi_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // surrogate inference beside the face kernels (created at the first
+  // surrogate step; default priority)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_prim = nullptr, ev_sur = nullptr;
   std::string err;
   // grid (host)
   int ni = 0, nj = 0, N = 0, bc_mode = 0;
@@ -240,6 +244,9 @@ int csi_create(csi_ctx **ctx, int device, void *hip_stream) {
 int csi_destroy(csi_ctx *c) {
   if (!c) return CSI_ERR_ARG;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->ev_prim) (void)hipEventDestroy(c->ev_prim);
+  if (c->ev_sur) (void)hipEventDestroy(c->ev_sur);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c->run;
   delete c;
   return CSI_OK;
@@ -488,6 +495,13 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   if (sur && !c->has_sur) return c->fail(CSI_ERR_STATE, "step: no surrogate installed");
   int rc = reset_flags(c);
   if (rc) return rc;
+  if (sur && !c->side) {
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_prim, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_sur, hipEventDisableTiming);
+    if ((rc = hip_check(c, e, "side stream"))) return rc;
+  }
   int every = p->check_every > 0 ? p->check_every : 50;
   csi_step_stats st{};
   st.bad_cell = -1;
@@ -528,9 +542,15 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     if (e == hipSuccess) e = c->run->prim(c->g, c->w, c->stream, true, c->prim_warm);
     c->prim_warm = true;
     if (E && e == hipSuccess) e = hipEventRecord(E[1], c->stream);
+    // the surrogate's inference needs only the primitives: it runs on the side
+    // stream while the face kernels run, and the cell kernel waits for it
+    if (sur && e == hipSuccess) e = hipEventRecord(c->ev_prim, c->stream);
+    if (sur && e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_prim, 0);
+    if (sur && e == hipSuccess) e = c->run->surrogate(c->g, c->w, c->side, true);
+    if (sur && e == hipSuccess) e = hipEventRecord(c->ev_sur, c->side);
     if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[2], c->stream);
-    if (sur && e == hipSuccess) e = c->run->surrogate(c->g, c->w, c->stream, true);
+    if (sur && e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_sur, 0);
     if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, sur ? 7 : 3, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[3], c->stream);
     const StallArgs stall{sur ? c->w.flags + FL_SURR_OFF : nullptr, int(it_start), c->sur_window, c->sur_ratio};
