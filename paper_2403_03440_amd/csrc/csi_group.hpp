@@ -451,14 +451,25 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
     RT rg[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) rg[q] = gather(r, gaddr[q]);
-    // the next step's record, behind the gather in the LDS queue
-    const int nslot = slot + 1 == DEPTH ? 0 : slot + 1;
-    if (e + 1 < NSTEP) {
-      if (rec_seen <= e + 1) rec_seen = lds_spin(&sy.rec_ready, e + 2, a.abort_flag, a.spin_limit, rsp, live);
-      nxt.load(ring + nslot * SLOT + cofs, kk);
-    }
-    lds_set(&sy.consumed, e + 1);
-    slot = nslot;
+    // The next step's record.  FP32: right behind the gather in the LDS
+    // queue.  FP64 (twice the words): only once the pushes are formed, since
+    // LDS results return in issue order and reads issued between a gather
+    // and its use hold up the gather's results (c2 forward sweep, split FP64
+    // 0.44 -> 0.41 ms, coupled FP64 0.59 -> 0.57 ms; the FP32 sweeps gain
+    // nothing there and the coupled FP32 one loses).  The empty statement
+    // and the scheduling barriers keep the compiler from hoisting the reads
+    // back above the push arithmetic.
+    auto next_record = [&]() {
+      const int nslot = slot + 1 == DEPTH ? 0 : slot + 1;
+      if (e + 1 < NSTEP) {
+        if (rec_seen <= e + 1) rec_seen = lds_spin(&sy.rec_ready, e + 2, a.abort_flag, a.spin_limit, rsp, live);
+        nxt.load(ring + nslot * SLOT + cofs, kk);
+      }
+      lds_set(&sy.consumed, e + 1);
+      slot = nslot;
+    };
+    constexpr bool LATE = sizeof(RT) == 8;
+    if (!LATE) next_record();
     RT y = cur.Dr[0] * rg[0];
 #pragma unroll
     for (int q = 1; q < G; ++q) y = fmad(cur.Dr[q], rg[q], y);
@@ -477,6 +488,12 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
     } else {
       p1 = push_comp<NS, NT, RT, P, FWD>(cur, 0, beta, x, nullptr, RT(0));
       p2 = push_comp<NS, NT, RT, P, FWD>(cur, 1, beta, x, nullptr, RT(0));
+    }
+    if (LATE) {
+      asm volatile("" : : "v"(p1), "v"(p2), "v"(x) : "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      next_record();
+      __builtin_amdgcn_sched_barrier(0);
     }
     // The pushes of a cell outside the grid reach only cells outside the grid
     // (the same j, or i beyond the last column), except the in-column push
