@@ -451,12 +451,14 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
     RT rg[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) rg[q] = gather(r, gaddr[q]);
-    // The next step's record.  FP32: right behind the gather in the LDS
-    // queue.  FP64 (twice the words): only once the pushes are formed, since
-    // LDS results return in issue order and reads issued between a gather
-    // and its use hold up the gather's results (c2 forward sweep, split FP64
+    // The next step's record.  FP32, and FP64 groups of more than 9 lanes:
+    // right behind the gather in the LDS queue.  FP64 groups of up to 9
+    // lanes: only once the pushes are formed, since LDS results return in
+    // issue order and reads issued between a gather and its use hold up the
+    // gather's results (5-species air, 512 x 256, forward sweep: split FP64
     // 0.44 -> 0.41 ms, coupled FP64 0.59 -> 0.57 ms; the FP32 sweeps gain
-    // nothing there and the coupled FP32 one loses).  The empty statement
+    // nothing and the coupled FP32 one loses, and so does the 15-lane
+    // coupled FP64 block of 11-species air, by 3 %).  The empty statement
     // and the scheduling barriers keep the compiler from hoisting the reads
     // back above the push arithmetic.
     auto next_record = [&]() {
@@ -468,7 +470,7 @@ __device__ __forceinline__ void compute_wave(const Geo &g, const GroupArgs &a, c
       lds_set(&sy.consumed, e + 1);
       slot = nslot;
     };
-    constexpr bool LATE = sizeof(RT) == 8;
+    constexpr bool LATE = sizeof(RT) == 8 && G <= 9;
     if (!LATE) next_record();
     RT y = cur.Dr[0] * rg[0];
 #pragma unroll
