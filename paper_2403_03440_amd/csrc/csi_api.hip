@@ -543,15 +543,17 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     c->prim_warm = true;
     if (E && e == hipSuccess) e = hipEventRecord(E[1], c->stream);
     // the surrogate's inference needs only the primitives: it runs on the side
-    // stream while the face kernels run, and the cell kernel waits for it
+    // stream while the face kernels run (and the cell kernel, where the
+    // diagonal blocks have a kernel of their own); the first kernel that reads
+    // its blocks waits for it
     if (sur && e == hipSuccess) e = hipEventRecord(c->ev_prim, c->stream);
     if (sur && e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_prim, 0);
     if (sur && e == hipSuccess) e = c->run->surrogate(c->g, c->w, c->side, true);
     if (sur && e == hipSuccess) e = hipEventRecord(c->ev_sur, c->side);
     if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[2], c->stream);
-    if (sur && e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_sur, 0);
-    if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, sur ? 7 : 3, true);
+    if (e == hipSuccess)
+      e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, sur ? 7 : 3, true, sur ? c->ev_sur : nullptr);
     if (E && e == hipSuccess) e = hipEventRecord(E[3], c->stream);
     const StallArgs stall{sur ? c->w.flags + FL_SURR_OFF : nullptr, int(it_start), c->sur_window, c->sur_ratio};
     if (e == hipSuccess) e = c->run->norms(c->w, c->stream, int(m), p->tol, true, stall);

@@ -38,8 +38,10 @@ class IRunner {
   // guess: start the temperature solves at the previous iteration's temperatures
   virtual hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable, bool guess = false) = 0;
   virtual hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
+  // sur_ready (optional): event after which the surrogate's blocks are in
+  // place; the launch makes the first kernel that reads them wait for it
   virtual hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
-                          bool stoppable) = 0;
+                          bool stoppable, hipEvent_t sur_ready = nullptr) = 0;
   virtual hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable,
                            StallArgs stall = StallArgs{nullptr, 0, 0, 0.0}) = 0;
   virtual hipError_t surrogate(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
@@ -83,7 +85,14 @@ template <int NS, int NT> class Runner : public IRunner {
   }
 
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
-                  bool stoppable) override {
+                  bool stoppable, hipEvent_t sur_ready = nullptr) override {
+    // with the diagonal blocks built by k_block only that kernel reads the
+    // surrogate's blocks, so the cell kernel runs beside the inference
+    const bool blk = NS >= BLOCK_NS_MIN && (flags & 2);
+    if (sur_ready && !blk) {
+      const hipError_t e = hipStreamWaitEvent(st, sur_ready, 0);
+      if (e != hipSuccess) return e;
+    }
     CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].S, w.grp[1].S}, w.src, w.flags + FL_SING, w.group_c,
               w.diag, w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
@@ -97,6 +106,10 @@ template <int NS, int NT> class Runner : public IRunner {
       if (flags & 2) {
         const BlockOut bo{{w.grp[0].S, w.grp[1].S}, w.Dinv, w.group_c, w.diag, w.sur.J, ddfail_counter(w.flags),
                           w.flags + FL_SURR_OFF, w.flags + FL_SING};
+        if (sur_ready) {
+          const hipError_t e = hipStreamWaitEvent(st, sur_ready, 0);
+          if (e != hipSuccess) return e;
+        }
         if (prec == 0) block<double>(g, w, st, mode, flags, bo, done);
         else block<float>(g, w, st, mode, flags, bo, done);
       }
