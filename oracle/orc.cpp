@@ -32,6 +32,7 @@ struct CellD {
 
 struct Face {
   double F[MAXV];
+  double Fv[MAXV] = {};                // viscous part of F (kept for the pins)
   double S = 0, nx = 0, ny = 0;       // length and unit normal (towards increasing index)
   double lam = 0, Uabs = 0;           // |U_f| + c_f and |U_f|
   double lvF = 0, lvC = 0, lvK = 0;   // viscous radii nu_f S_f / V_f (flow, species, coupled)
@@ -578,7 +579,7 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
       double Fv[MAXV];
       interior_viscous(L, R, c->xc[c->ci(I - 1, j)], c->yc[c->ci(I - 1, j)], c->xc[c->ci(I, j)],
                        c->yc[c->ci(I, j)], I, j, I, j + 1, F.nx, F.ny, Fv);
-      for (int k = 0; k < nv; ++k) F.F[k] += Fv[k];
+      for (int k = 0; k < nv; ++k) { F.F[k] += Fv[k]; F.Fv[k] = Fv[k]; }
     }
   }
   // j-faces
@@ -597,7 +598,7 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
       double Fv[MAXV];
       interior_viscous(L, R, c->xc[c->ci(i, J - 1)], c->yc[c->ci(i, J - 1)], c->xc[c->ci(i, J)],
                        c->yc[c->ci(i, J)], i, J, i + 1, J, F.nx, F.ny, Fv);
-      for (int k = 0; k < nv; ++k) F.F[k] += Fv[k];
+      for (int k = 0; k < nv; ++k) { F.F[k] += Fv[k]; F.Fv[k] = Fv[k]; }
     } else if (J == 0 && c->bc_mode == 0) {
       // isothermal, no-slip, non-catalytic wall: face values at the wall,
       // normal gradient from the wall value and the first cell centre
@@ -625,7 +626,7 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
       for (int s = 0; s < ns; ++s) { g.gY[s][0] = 0.0; g.gY[s][1] = 0.0; }
       double Fv[MAXV], qn;
       viscous_flux(m, fv, g, F.nx, F.ny, Fv, &qn);
-      for (int k = 0; k < nv; ++k) F.F[k] += Fv[k];
+      for (int k = 0; k < nv; ++k) { F.F[k] += Fv[k]; F.Fv[k] = Fv[k]; }
       c->qw[i] = -qn;
     }
   }
@@ -1058,6 +1059,14 @@ int orc_get(orc_ctx *c, const char *name, double *out) {
   if (n == "DK") return put(c->DK);
   if (n == "DF") return put(c->DF);
   if (n == "DC") return put(c->DC);
+  if (n == "FvI" || n == "FvJ") {  // viscous face fluxes [nv][faces] (i faces (ni+1)*nj, j faces ni*(nj+1))
+    const std::vector<Face> &fa = n == "FvI" ? c->fI : c->fJ;
+    if (fa.empty()) return c->fail(-3, "faces not computed");
+    const size_t nfa = fa.size();
+    for (int k = 0; k < c->m.nv(); ++k)
+      for (size_t f = 0; f < nfa; ++f) out[k * nfa + f] = fa[f].Fv[k];
+    return 0;
+  }
   if (n == "T" || n == "Tv" || n == "p" || n == "c") {
     if (c->cells.empty()) return c->fail(-3, "primitives not computed");
     for (int p = 0; p < N; ++p) {
@@ -1157,6 +1166,14 @@ int orc_point_flux(orc_ctx *c, const double *q, double nx, double ny, double *F)
   Prim<double> P;
   if (!recover<double>(c->m, q, P)) return -4;
   phys_flux<double>(c->m, q, P, nx, ny, F);
+  return 0;
+}
+
+int orc_point_hlle(orc_ctx *c, const double *qL, const double *qR, double nx, double ny, double *F) {
+  if (!c || !c->has_mech) return -1;
+  CellD L, R;
+  if (!make_cell(c->m, qL, L) || !make_cell(c->m, qR, R)) return c->fail(-4, "non-physical point state");
+  hlle(c->m, L, R, nx, ny, F);
   return 0;
 }
 

@@ -81,7 +81,8 @@ int orc_wall_heat_flux(orc_ctx *ctx, double *qw, double *q_stag);
 
 /* named arrays for tests: "R" [nv][N], "dtau" [N], "omega" [nv][N], "dqs" "dq" [nsol][N],
  * "T" "Tv" "p" "c" [N], "qw" [ni], "dK" "dF" "dC" [N], "JK" [nb*nb][N], "JC" [ns*ns][N],
- * "Jve" [nf][N], "DK" [nb*nb][N], "DF" [nf*nf][N], "DC" [ns*ns][N] (row-major blocks) */
+ * "Jve" [nf][N], "DK" [nb*nb][N], "DF" [nf*nf][N], "DC" [ns*ns][N] (row-major blocks),
+ * "FvI" [nv][(ni+1)*nj], "FvJ" [nv][ni*(nj+1)] (viscous part of the face fluxes F.n, per unit length) */
 int orc_get(orc_ctx *ctx, const char *name, double *out);
 
 /* dense global operator on small grids: unknown index = cell * nsol + k;
@@ -96,6 +97,8 @@ int orc_point_production(orc_ctx *ctx, const double *rho_s, double T, double Tv,
 int orc_point_prim(orc_ctx *ctx, const double *q, double *T, double *Tv, double *p, double *c);
 int orc_point_flux_jacobian(orc_ctx *ctx, const double *q, double nx, double ny, double *A);
 int orc_point_flux(orc_ctx *ctx, const double *q, double nx, double ny, double *F);
+/* HLLE face flux between left state qL and right state qR, unit normal (nx, ny) from L to R */
+int orc_point_hlle(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double *F);
 int orc_point_source_jacobian(orc_ctx *ctx, const double *q, int which, double *J);
 
 #ifdef __cplusplus

@@ -186,7 +186,8 @@ class Oracle:
                   "dq": (self.nsol(mode), N), "T": (N,), "Tv": (N,), "p": (N,), "c": (N,),
                   "qw": (self.ni,), "dK": (N,), "dF": (N,), "dC": (N,), "JK": (m.nb, m.nb, N),
                   "JC": (m.ns, m.ns, N), "Jve": (m.nf, N), "DK": (m.nb, m.nb, N), "DF": (m.nf, m.nf, N),
-                  "DC": (m.ns, m.ns, N)}
+                  "DC": (m.ns, m.ns, N), "FvI": (m.nv, (self.ni + 1) * self.nj),
+                  "FvJ": (m.nv, self.ni * (self.nj + 1))}
         out = np.zeros(shapes[name])
         self._check(self.L.orc_get(self.ctx, name.encode(), out.ctypes.data_as(_dp)))
         return out
@@ -227,6 +228,13 @@ class Oracle:
         F = np.zeros(self.mech.nv)
         a, p = _d(q)
         self._check(self.L.orc_point_flux(self.ctx, p, C.c_double(nx), C.c_double(ny), F.ctypes.data_as(_dp)))
+        return F
+
+    def point_hlle(self, qL, qR, nx, ny):
+        F = np.zeros(self.mech.nv)
+        a, pl = _d(qL)
+        b, pr = _d(qR)
+        self._check(self.L.orc_point_hlle(self.ctx, pl, pr, C.c_double(nx), C.c_double(ny), F.ctypes.data_as(_dp)))
         return F
 
     def point_flux_jacobian(self, q, nx, ny):
