@@ -3,18 +3,23 @@
 A step is one pseudo-time iteration of the whole path: primitives, residual
 with chemistry, local time step, diagonal blocks with the source Jacobian, the
 LU-SGS forward and backward sweeps, the consistency correction and update, and
-the residual norms.  The default workload is the 512 x 256 polar blunt-body
-grid with two-temperature 5-species air at CFL 100 from a uniform free stream
-(synthetic input; there is no dataset).
+the residual norms.  The default workload is the largest single-GPU case: the
+2048 x 1024 polar blunt-body grid with a seeded 20-species / 60-reaction
+one-temperature mechanism at CFL 1000 from a uniform free stream (synthetic
+input; there is no dataset).
 
 Reported per variant (coupled / split, FP64 / mixed, exact / surrogate
-species Jacobian block):
-  * cell-iterations per second over K timed steps after W warm-up steps;
-  * time and iterations to a 1e-8 drop of the density residual, from the free
-    stream, with the same CFL ramp for every variant.
-The surrogate network is trained first on samples of the exact solver's own
-iterations (collection and training times reported separately).  The headline
-`value` is the split mixed-precision solver with the surrogate block.
+species Jacobian block): cell-iterations per second over K timed steps after
+W warm-up steps, with per-phase times.  The headline `value` is the split
+mixed-precision solver with the surrogate block.  The surrogate network is
+trained first on samples of the exact solver's own iterations (sampling and
+training times reported separately).
+
+Time to a 1e-8 drop of the density residual from the free stream, with the
+same CFL ramp for every variant, is measured on a smaller case (512 x 256,
+5-species two-temperature air, CFL 100; `--tol-config`), where every variant
+reaches it within seconds, together with the surrogate's amortised total
+(sampling + training + solve); `--converge` also runs it on the main workload.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -32,11 +37,17 @@ sys.path.insert(0, ROOT)
 
 GEOM_WORDS = 5  # cell volume + four face lengths/normals summarised as one word each
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # vector FP64: 256 CUs x 2.4 GHz x 128 flops per clock per CU
 VARIANTS = {  # name: (mode, correction kind, precision, species Jacobian 0 exact / 1 surrogate)
     "split64": (1, 2, 0, 0), "coupled64": (0, 0, 0, 0), "splitmixed": (1, 2, 1, 0), "coupledmixed": (0, 0, 1, 0),
     "splitmixed_mlp": (1, 2, 1, 1)}
 HEADLINE = "splitmixed_mlp"
-SWEEP_SOURCES = ["csi_group.hpp", "csi_kernels.hpp", "csi_sweep.hpp", "csi_phys.hpp"]
+KERNEL_SOURCES = {"sweep_fwd": ["csi_group.hpp", "csi_kernels.hpp", "csi_sweep.hpp", "csi_phys.hpp"],
+                  "sweep_bwd": ["csi_group.hpp", "csi_kernels.hpp", "csi_sweep.hpp", "csi_phys.hpp"],
+                  "block": ["csi_block.hpp", "csi_kernels.hpp", "csi_phys.hpp"],
+                  "cell": ["csi_kernels.hpp", "csi_phys.hpp"]}
+KERNEL_NAMES = {"sweep_fwd": "k_group_sweep (forward)", "sweep_bwd": "k_group_sweep (backward)",
+                "block": "k_block", "cell": "k_cell"}
 
 
 MECH_TEXT = {"air5": "5-species air", "air11": "11-species ionised air",
@@ -63,9 +74,33 @@ def b_alg_sweep(m, mode, precision):
     return (m.nv + GEOM_WORDS) * 8 + 2 * nsol(m, mode) * w
 
 
-def sweep_source_hash():
+def chem_flops(m):
+    """FP64 flops per cell of the exact chemical source Jacobian: per reaction
+    about 40 for the rates (transcendentals counted once) plus a multiply-add
+    per entry it adds to the Jacobian (the rows of the species it changes,
+    the columns of the species its rate depends on: every species through a
+    third body)."""
+    import numpy as np
+    nu_f, nu_b = np.asarray(m.nu_f), np.asarray(m.nu_b)
+    tot = 0
+    for r in range(m.nr):
+        rows = int(np.count_nonzero(nu_b[r] - nu_f[r]))
+        cols = m.ns if m.third[r] else int(np.count_nonzero(nu_f[r] + nu_b[r]))
+        tot += 40 + 2 * rows * cols
+    return tot
+
+
+def block_flops(m, mode):
+    """Algorithmic FP64 flops per cell of the diagonal-block kernel: the
+    chemical source Jacobian and the factorisation (2 n^3 / 3) of the block
+    (n = nb coupled, ns split)."""
+    n = m.nb if mode == 0 else m.ns
+    return chem_flops(m) + 2.0 * n ** 3 / 3.0
+
+
+def source_hash(kernel):
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2403_03440_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -73,21 +108,26 @@ def sweep_source_hash():
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary, if
-    that summary was taken on the current sweep sources; else None."""
+    that summary was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     hm = re.search(r"source hash:\s*`?([0-9a-f]{16})", txt)
     tm = re.search(r"HBM bytes per launch:\s*([0-9.eE+]+)", txt)
-    if not hm or not tm or hm.group(1) != sweep_source_hash():
+    if not hm or not tm or hm.group(1) != source_hash(kernel):
         return None
     return float(tm.group(1))
+
+
+JC_READING = 0  # split species block reading (csi_set_species_jacobian)
 
 
 def new_solver(csi, I, cfg, m, x, y, fs, sur=None):
     s = csi.Solver((x, y), m, fs)
     s.set_state(s.initial_state(*I.initial_prims(cfg, m)))
+    if JC_READING:
+        s.set_species_jacobian(JC_READING)
     if sur is not None:
         s.set_surrogate(sur["params"], sur["scales"])
     return s
@@ -136,6 +176,10 @@ def throughput(csi, I, cfg, m, x, y, fs, variant, steps, warmup, sur=None):
            "b_alg_per_cell_iter": b_alg_iter(m, mode, prec)}
     if jac:
         out["surrogate_accept_frac"] = 1.0 - st["n_dd_fallback"] / float(cfg.ni * cfg.nj * n)
+        out["surrogate_off_at"] = st["surrogate_off_at"]
+        # a divergence fallback repeats the call's iterations with the exact
+        # block: the time then covers both passes
+        out["surrogate_diverged"] = st["surrogate_diverged"]
     return out
 
 
@@ -231,7 +275,7 @@ def scaling(csi, I, ns_list, steps, warmup):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ph = {k: p["ms_per_iter"] for k, p in s.phase_times().items() if isinstance(p, dict)}
-            imp = ph["cell"] + ph["sweep_fwd"] + ph["sweep_bwd"] + ph["update"]
+            imp = ph["cell"] + ph["block"] + ph["sweep_fwd"] + ph["sweep_bwd"] + ph["update"]
             rows.append({"ns": ns, "variant": v, "ms_per_iter": 1e3 * dt / steps, "implicit_ms": imp, "phases": ph})
             print(f"# ns {ns} {v}: {1e3 * dt / steps:.3f} ms/it, implicit {imp:.3f} ms", file=sys.stderr, flush=True)
             del s
@@ -255,37 +299,48 @@ def oracle_threads():
     return max(n, 1)
 
 
-def cpu_baseline(I, cfg, m, x, y, fs, budget_s=20.0):
-    """The oracle on the host cores over a bounded sample: whole iterations of
-    the same workload (split, CC2, FP64) from the free stream until about
-    budget_s seconds have passed."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            names = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+        return names[0] if names else "unknown"
+    except OSError:
+        return "unknown"
+
+
+def cpu_baseline(I, cfg, m, budget_s=20.0, sample_grid=(128, 64)):
+    """The oracle on the host cores over a bounded sample of the workload: the
+    same mechanism, free stream and CFL schedule on a coarser grid of the same
+    geometry (its cost per cell-iteration does not depend on the grid size),
+    whole split-CC2 FP64 iterations from the free stream until about budget_s
+    seconds have passed."""
     from oracle import orc
     threads = oracle_threads()
-    o = orc.setup((x, y), m, fs, threads=threads)
-    o.set_state(o.prim_to_cons(*I.initial_prims(cfg, m)))
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.step(1, 2, cfg.cfl, 1, ramp=cfg.ramp, it0=n)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 200:
-            break
-    dt = time.perf_counter() - t0
-    out = {"value": cfg.ni * cfg.nj * n / dt, "unit": "cell-iters/s", "cores": threads, "kind": "oracle",
-           "sample": f"first {n} split-CC2 FP64 iterations of the {cfg.ni}x{cfg.nj} workload from the free "
-                     f"stream ({dt:.1f} s, {threads} OpenMP threads)"}
-    # the same iterations on one thread (a shorter sample)
-    o1 = orc.setup((x, y), m, fs, threads=1)
-    o1.set_state(o1.prim_to_cons(*I.initial_prims(cfg, m)))
-    t0 = time.perf_counter()
-    n1 = 0
-    while True:
-        o1.step(1, 2, cfg.cfl, 1, ramp=cfg.ramp, it0=n1)
-        n1 += 1
-        if time.perf_counter() - t0 > budget_s / 2 or n1 >= 50:
-            break
-    dt1 = time.perf_counter() - t0
-    out["value_1_thread"] = cfg.ni * cfg.nj * n1 / dt1
+    ni, nj = sample_grid if cfg.ni * cfg.nj > sample_grid[0] * sample_grid[1] else (cfg.ni, cfg.nj)
+    scfg = I.Config(cfg.name, ni, nj, cfg.mech, cfg.two_temp, cfg.cfl, cfg.u_inf, ramp=cfg.ramp)
+    x, y = scfg.grid()
+    fs = I.freestream_prims(scfg, m)
+
+    def run(nthreads, budget, cap):
+        o = orc.setup((x, y), m, fs, threads=nthreads)
+        o.set_state(o.prim_to_cons(*I.initial_prims(scfg, m)))
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            o.step(1, 2, scfg.cfl, 1, ramp=scfg.ramp, it0=n)
+            n += 1
+            if time.perf_counter() - t0 > budget or n >= cap:
+                break
+        return n, time.perf_counter() - t0
+
+    n, dt = run(threads, budget_s, 200)
+    out = {"value": ni * nj * n / dt, "unit": "cell-iters/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n} split-CC2 FP64 iterations from the free stream of the same mechanism, flow and "
+                     f"CFL schedule on a {ni}x{nj} grid of the same geometry ({dt:.1f} s, {threads} OpenMP "
+                     f"threads)",
+           "cpu": cpu_model(), "logical_cpus_visible": len(os.sched_getaffinity(0))}
+    n1, dt1 = run(1, budget_s / 2, 50)
+    out["value_1_thread"] = ni * nj * n1 / dt1
     out["sample_1_thread"] = f"first {n1} of the same iterations on 1 thread ({dt1:.1f} s)"
     return out
 
@@ -302,19 +357,83 @@ def copy_probe(gib=1.0, reps=3):
     print(f"# copy probe: {reps} copies of {4 * n} bytes", file=sys.stderr, flush=True)
 
 
+def roofline(m, mode, prec, ph, N, workload):
+    """Roofline entry of the headline variant's dominant kernel (the largest
+    per-launch time among the block kernel and the two sweeps, one launch
+    each per iteration, HIP events on the library's stream)."""
+    cands = {k: ph.get(k, 0.0) for k in ("block", "sweep_fwd", "sweep_bwd") if ph.get(k, 0.0) > 0.0}
+    kernel = max(cands, key=cands.get)
+    ms = cands[kernel]
+    traffic = measured_traffic(kernel, workload)
+    if kernel == "block":
+        fl = block_flops(m, mode)
+        ach = fl * N / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": KERNEL_NAMES[kernel],
+                "ms_per_launch": ms, "alg_flops_per_cell": fl, "cells_per_launch": N,
+                "alg_flops_per_launch": fl * N,
+                "flops_model": "exact chemical source Jacobian (rates + one multiply-add per Jacobian entry each "
+                               "reaction adds) + 2 n^3 / 3 factorisation of the n x n block, FP64"}
+    bytes_launch = b_alg_sweep(m, mode, prec) * N
+    ach = bytes_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": KERNEL_NAMES[kernel], "ms_per_launch": ms,
+            "alg_bytes_per_cell": b_alg_sweep(m, mode, prec), "cells_per_launch": N,
+            "alg_bytes_per_launch": bytes_launch}
+
+
+def workload_text(cfg, m):
+    return (f"{cfg.name}: {cfg.ni}x{cfg.nj} polar blunt body, {MECH_TEXT[cfg.mech]} "
+            f"{'2T' if m.two_temp else '1T'}, u {cfg.u_inf:g} m/s, CFL {cfg.cfl:g} (ramp over {cfg.ramp} "
+            f"iterations), uniform free-stream start")
+
+
+def tol_leg(csi, I, name, names, tol, max_iter, epochs, snapshots):
+    """Every variant from the free stream to the tolerance on one workload,
+    the converged states against the split FP64 run's, and the surrogate's
+    amortised cost (sampling + training + solve) against the exact block."""
+    cfg = I.CONFIGS[name]
+    m = cfg.mechanism()
+    x, y = cfg.grid()
+    fs = I.freestream_prims(cfg, m)
+    sur, info = None, None
+    if any(VARIANTS[v][3] for v in names):
+        print(f"# {name}: surrogate sampling and training", file=sys.stderr, flush=True)
+        sur, info = train_surrogate(csi, I, cfg, m, x, y, fs, epochs, snapshots)
+    res = {v: {"to_tol": converge(csi, I, cfg, m, x, y, fs, v, tol, max_iter, sur)} for v in names}
+    compare_to_fp64(m, res)
+    out = {"workload": workload_text(cfg, m), "cells": cfg.ni * cfg.nj,
+           "variants": {v: r["to_tol"] for v, r in res.items()}, "surrogate_training": info}
+    t = out["variants"]
+    if sur is not None and t.get(HEADLINE, {}).get("converged") and t.get("splitmixed", {}).get("converged"):
+        tot = info["collect_s"] + info["train_s"] + t[HEADLINE]["seconds"]
+        out["surrogate_amortised"] = {
+            "collect_s": info["collect_s"], "train_s": info["train_s"], "solve_s": t[HEADLINE]["seconds"],
+            "total_s": tot, "split_mixed_exact_block_s": t["splitmixed"]["seconds"],
+            "gain_s": t["splitmixed"]["seconds"] - tot,
+            "iterations_vs_exact_block": t[HEADLINE]["iters"] - t["splitmixed"]["iters"]}
+    if t.get("coupled64", {}).get("converged") and t.get(HEADLINE, {}).get("converged"):
+        out["speedup_time_to_tol_vs_coupled64"] = t["coupled64"]["seconds"] / t[HEADLINE]["seconds"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c5")
     ap.add_argument("--variants", default="splitmixed_mlp,splitmixed,split64,coupled64,coupledmixed")
-    ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
-    ap.add_argument("--snapshots", type=int, default=16, help="surrogate training snapshots (all cells each)")
+    ap.add_argument("--epochs", type=int, default=0, help="surrogate training epochs (0: 5 on c5, else 20)")
+    ap.add_argument("--snapshots", type=int, default=0,
+                    help="surrogate training snapshots, all cells each (0: 2 on c5, else 16)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=12000)
-    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--converge", action="store_true", help="also run every variant to the tolerance on --config")
+    ap.add_argument("--tol-config", default="c2", help="workload of the time-to-tolerance legs ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--species-jacobian", type=int, default=0,
+                    help="split species block: 0 fixed T, Tv; 1 fixed velocities and internal energy")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--scaling", default="", help="species counts (e.g. 5,11,16,20,32): implicit-step time vs ns "
                                                  "in non-reacting flow, instead of the workload above")
@@ -331,6 +450,9 @@ def main():
         print(json.dumps(scaling(csi, I, [int(v) for v in args.scaling.split(",")], args.steps, args.warmup)))
         return
     cfg = I.CONFIGS[args.config]
+    big = cfg.ni * cfg.nj > 1_000_000
+    epochs = args.epochs or (5 if big else 20)
+    snapshots = args.snapshots or (2 if big else 16)
     m = cfg.mechanism()
     x, y = cfg.grid()
     fs = I.freestream_prims(cfg, m)
@@ -338,15 +460,17 @@ def main():
     names = [v for v in args.variants.split(",") if v]
     if HEADLINE not in names:
         names.insert(0, HEADLINE)
+    global JC_READING
+    JC_READING = args.species_jacobian
     sur, sur_info = None, None
     if any(VARIANTS[v][3] for v in names):
         print("# surrogate: sampling and training", file=sys.stderr, flush=True)
-        sur, sur_info = train_surrogate(csi, I, cfg, m, x, y, fs, args.epochs, args.snapshots)
+        sur, sur_info = train_surrogate(csi, I, cfg, m, x, y, fs, epochs, snapshots)
     res = {}
     for v in names:
         print(f"# throughput {v}", file=sys.stderr, flush=True)
         res[v] = throughput(csi, I, cfg, m, x, y, fs, v, args.steps, args.warmup, sur)
-    if not args.no_converge:
+    if args.converge:
         for v in names:
             res[v]["to_tol"] = converge(csi, I, cfg, m, x, y, fs, v, args.tol, args.max_iter, sur)
         compare_to_fp64(m, res)
@@ -354,16 +478,7 @@ def main():
         copy_probe()
     head = res[HEADLINE]
     mode, _, prec, _ = VARIANTS[HEADLINE]
-    ph = head["phases_ms_per_iter"]
-    kernel = "sweep_fwd" if ph["sweep_fwd"] >= ph["sweep_bwd"] else "sweep_bwd"
-    ms_launch = ph[kernel]
-    bytes_launch = b_alg_sweep(m, mode, prec) * N
-    ach = bytes_launch / (ms_launch * 1e-3) / 1e9
-    traffic = measured_traffic(kernel, cfg.name)
-    chain = cfg.ni + cfg.nj - 1
-    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": traffic, "kernel": kernel, "ms_per_launch": ms_launch, "alg_bytes_per_launch": bytes_launch,
-            "hyperplane_steps_per_launch": chain, "us_per_hyperplane_step": 1e3 * ms_launch / chain}
+    roof = roofline(m, mode, prec, head["phases_ms_per_iter"], N, cfg.name)
     whole = {"alg_GBs": b_alg_iter(m, mode, prec) * head["cell_iters_per_s"] / 1e9}
     whole["frac"] = whole["alg_GBs"] / HBM_PEAK_GBS
     dtype = "f32+f64" if prec == 1 else "f64"
@@ -375,28 +490,23 @@ def main():
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {cfg.ni}x{cfg.nj} polar blunt body, {MECH_TEXT[cfg.mech]} "
-                               f"{'2T' if m.two_temp else '1T'}, u {cfg.u_inf:g} m/s, CFL {cfg.cfl:g} "
-                               f"(ramp over {cfg.ramp} iterations), "
-                               f"split solver, FP32 sweeps + FP64 residual/chemistry/CC2, species Jacobian block "
-                               f"from the BF16 surrogate network with exact fallback, uniform free-stream start",
+        "config": {"workload": workload_text(cfg, m) + ", headline: split solver, FP32 sweeps and block "
+                               "inverses + FP64 residual/chemistry/CC2, species Jacobian block from the BF16 "
+                               "surrogate network with exact fallback",
                    "cells": N},
         "roofline": roof,
         "whole_iteration_hbm": whole,
         "variants": res,
         "surrogate_training": sur_info,
     }
+    if "coupled64" in res:
+        out["speedup_vs_coupled64"] = {v: r["cell_iters_per_s"] / res["coupled64"]["cell_iters_per_s"]
+                                       for v, r in res.items()}
+    if args.tol_config:
+        out["time_to_tol"] = tol_leg(csi, I, args.tol_config, names, args.tol, args.max_iter, 20, 16)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
-        cb = cpu_baseline(I, cfg, m, x, y, fs)
-        # the oracle follows the split FP64 trajectory: its time to the tolerance
-        # projected from its seconds per iteration and that run's iteration count
-        t64 = res.get("split64", {}).get("to_tol", {})
-        if t64.get("converged"):
-            cb["projected_seconds_to_tol"] = t64["iters"] * N / cb["value"]
-            cb["projection"] = (f"{t64['iters']} iterations (split FP64 run to {args.tol:g}) x the sample's "
-                                f"seconds per iteration")
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline(I, cfg, m)
     print(json.dumps(out))
 
 

@@ -96,16 +96,33 @@ int csi_create(csi_ctx **ctx, int device, void *hip_stream);
 int csi_destroy(csi_ctx *ctx);
 const char *csi_last_error(const csi_ctx *ctx);
 
-/* Grid nodes x_nodes, y_nodes: host [(nj+1)][(ni+1)], i fastest.  bc_mode 0:
- * isothermal no-slip non-catalytic wall at j = 0 (T_wall), free-stream far
- * field at j = nj, zero-gradient outflow at i = 0 and i = ni; bc_mode 1:
- * free stream on all four sides. */
+/* Structured grid of the finite-volume form of Eq. (iterate) (Section 2.2:
+ * the generalised-coordinate fluxes become face fluxes F.n S_f, 1/J becomes the
+ * cell area V_P).  Grid nodes x_nodes, y_nodes: host [(nj+1)][(ni+1)], i
+ * fastest, copied; cell (i, j) has nodes (i..i+1, j..j+1).  Cell areas
+ * (shoelace) and face vectors (one per face, shared by its two cells) are
+ * derived here.  bc_mode 0: isothermal no-slip non-catalytic wall at j = 0
+ * (T_wall; the isothermal wall of the paper's cylinder case, Section 3.2),
+ * free-stream far field at j = nj, zero-gradient outflow at i = 0 and i = ni;
+ * bc_mode 1: free stream on all four sides (the far-field box of Section 3.1).
+ * Errors: CSI_ERR_ARG for ni, nj < 1, more than 2e9 cells, null arrays,
+ * T_wall <= 0 or another bc_mode. */
 int csi_set_grid(csi_ctx *ctx, int ni, int nj, const double *x_nodes, const double *y_nodes, double T_wall,
                  int bc_mode);
-/* Compiled species counts: 2, 3, 5 and 11 (one and two temperatures), 16, 20
- * and 32 (one temperature); others return CSI_ERR_UNSUPPORTED. */
+/* Thermochemical model of the governing equations (Section 2.1, Eq. (govern)
+ * and Eq. (flux): ns species continuity equations with source omega_s, the
+ * mixture momentum and total energy, and in two temperatures the vibrational-
+ * electronic energy with its source omega_ve; the thermodynamic, kinetic and
+ * transport laws the paper defers to its references are fixed by the tables of
+ * csi_mechanism).  The host tables are copied.  Compiled species counts: 2, 3,
+ * 5 and 11 (one and two temperatures), 16, 20 and 32 (one temperature); others
+ * return CSI_ERR_UNSUPPORTED; CSI_ERR_ARG for nr > 64 or bad tables. */
 int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
-/* free stream from primitives (rho_s [ns] host, u, v, T, Tv) */
+/* Free-stream state of the far-field boundary (the Dirichlet far field of
+ * Section 3; also the uniform flow of the Section 3.1 box) from primitives:
+ * partial densities rho_s [ns] (host, copied), velocity (u, v), temperatures
+ * T and Tv (Tv ignored in one temperature).  Errors: CSI_ERR_ARG for a
+ * non-positive temperature; CSI_ERR_STATE before set_mechanism. */
 int csi_set_freestream(csi_ctx *ctx, const double *rho_s, double u, double v, double T, double Tv);
 int csi_workspace_bytes(const csi_ctx *ctx, size_t *bytes);
 /* dev_ptr: device memory of at least csi_workspace_bytes, 256-byte aligned; caller owns it */
@@ -126,6 +143,26 @@ int csi_residual(csi_ctx *ctx, double cfl, double *norms);
  * CSI_JAC_SURROGATE (split species block from the installed network, exact
  * fallback per cell when the diagonal-dominance check fails). */
 int csi_implicit_op(csi_ctx *ctx, int mode, int precision, int jac);
+/* Dual time stepping for unsteady flows (Section 2.2, Eq. (dualimplicit) and
+ * Eq. (linearizedimplicit)): with dt > 0 every later residual is the unsteady
+ * residual R(Q) + V [(1 + theta)(Q - Q^n) - theta (Q^n - Q^{n-1})] / dt (its
+ * norms included) and every diagonal block gains (1 + theta) V / dt next to
+ * V / dtau, so that the pseudo-time iterations of csi_step converge to the
+ * implicit physical time step.  theta = 0: first-order backward Euler;
+ * theta = 1/2: the second-order backward difference (the paper's text gives
+ * theta = 2 for second order, which makes the scheme first order; 1/2 is the
+ * value for which the discretisation is second order).  dt = 0 (default):
+ * steady.  Errors: CSI_ERR_ARG for a negative or non-finite dt or theta. */
+int csi_set_physical_time(csi_ctx *ctx, double dt, double theta);
+/* Start a physical time step: Q^{n-1} <- Q^n, Q^n <- Q (csi_set_state sets
+ * both levels to the state), and the next csi_step starts its residual drop
+ * and CFL ramp afresh.  Errors: CSI_ERR_STATE without a bound state. */
+int csi_advance_time(csi_ctx *ctx);
+/* Set the time levels Q^n and Q^{n-1} directly (restart of an unsteady run):
+ * FP64 [nv][nj][ni] each, host (on_device = 0) or device memory, copied.
+ * Errors: CSI_ERR_STATE without a bound state. */
+int csi_set_time_levels(csi_ctx *ctx, const double *qn, const double *qnm1, int on_device);
+
 /* closure (coupled) or CC1 / CC2 (split) and the FP64 update of Q (paper Section 2.3) */
 int csi_consistency_correct(csi_ctx *ctx, int kind);
 /* iterate: residual -> implicit_op -> consistency_correct, with a CFL ramp and stop test.
@@ -136,7 +173,28 @@ int csi_consistency_correct(csi_ctx *ctx, int kind);
  * per call.  Without the surrogate, or after that, such iterations return
  * CSI_ERR_NONFINITE / CSI_ERR_SINGULAR. */
 int csi_step(csi_ctx *ctx, const csi_step_params *p, csi_step_stats *s);
-/* wall heat flux into the wall per wall cell (host [ni]) and its value at the stagnation line */
+/* Which source Jacobian the split species block carries (Section 2.3, the
+ * component operator solves Q_C with the flow variables unchanged; the paper
+ * does not say which variables the chemical source is differentiated at).
+ * reading 0 (default): J_C = d omega_s / d rho_r at fixed T, Tv.  reading 1:
+ * at fixed velocities and fixed internal (and vibrational) energy densities,
+ * so that the temperatures follow the composition (the Jacobian of an
+ * adiabatic constant-volume reactor): J_C + d omega_s/dT dT/d rho_r
+ * (+ the Tv term).  Reading 1 applies to the exact block only (the
+ * surrogate's block stays at fixed T, Tv) and needs ns >= 5
+ * (CSI_ERR_UNSUPPORTED otherwise).  Errors: CSI_ERR_ARG for another value,
+ * CSI_ERR_STATE before set_mechanism.  Reset by set_mechanism. */
+int csi_set_species_jacobian(csi_ctx *ctx, int reading);
+
+/* Wall heat flux, the quantity whose convergence the paper tracks beside the
+ * residual (Section 3.2 and later cases; conduction only: the wall is
+ * non-catalytic, so no diffusive enthalpy flux): per wall cell i
+ * q_w = k (T_i0 - T_w) / d_i + k_ve (Tv_i0 - T_w) / d_i with the wall-face
+ * conductivities and d_i the cell-centre-to-wall distance, from the last
+ * csi_residual; host [ni], nullable.  q_stag (host, nullable): mean of the two
+ * cells beside the stagnation line (ni even) or the middle cell.  Synchronises
+ * with the device.  Errors: CSI_ERR_STATE without a bound state or on a grid
+ * without a wall (bc_mode 1). */
 int csi_wall_heat_flux(csi_ctx *ctx, double *qw, double *q_stag);
 /* residual-norm history of csi_step calls: host [2*n] (r_rho, r_E per iteration) */
 int csi_norm_history(csi_ctx *ctx, int n, double *hist);
@@ -157,9 +215,10 @@ int csi_set_sweep(csi_ctx *ctx, int schedule);
  * enable; on = 2 also records a per-strip trace of the group-schedule sweeps,
  * read with csi_get_array(ctx, "sweep_trace"); 0 disables both).
  * csi_phase_times returns the accumulated milliseconds of the
- * phases [prim, faces, cell, norms, sweep_fwd, sweep_bwd, update] (ms[0..6])
- * and the number of timed iterations in ms[7]; reset = 1 clears the
- * accumulators.  ms must hold 8 doubles. */
+ * phases [prim, faces, cell, block, norms, sweep_fwd, sweep_bwd, update]
+ * (ms[0..7]; cell: the cell kernel, block: the diagonal-block kernel of
+ * ns >= 5, zero below) and the number of timed iterations in ms[8];
+ * reset = 1 clears the accumulators.  ms must hold 9 doubles. */
 int csi_set_timing(csi_ctx *ctx, int on);
 int csi_phase_times(csi_ctx *ctx, double *ms, int reset);
 
@@ -234,7 +293,10 @@ int csi_mlp_train_step(csi_ctx *ctx, const csi_mlp_batch *b, float *m, float *v,
 
 /* Training samples from the bound state: for cells 0..n-1 (n = min(N,
  * max_samples), returned in *n_written) the raw features x_raw [n][ns + 3] and
- * the exact J_C [n][ns * ns] (FP32). */
+ * the exact J_C [n][ns * ns] (FP32).  There is no seed argument: the call is
+ * deterministic and takes every cell of the state (the training set is whole
+ * snapshots of the solver's own iterates); the seeded draw happens in the
+ * training, whose batch order comes from a seeded permutation of the rows. */
 int csi_sample_jacobians(csi_ctx *ctx, int max_samples, float *x_raw, float *jc, int *n_written);
 /* Install a trained network for CSI_JAC_SURROGATE (split form only):
  * params [n_params] (device, copied into the workspace), scales (host,

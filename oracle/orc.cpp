@@ -59,6 +59,13 @@ struct orc_ctx {
   std::vector<int> pivK, pivF, pivC;
   std::vector<double> dqs, dq, qw;
   int last_mode = -1;
+  // split species block: 0 = d omega / d rho_r at fixed T, Tv; 1 = at fixed
+  // momenta and energies (Q_F unchanged), the temperatures following
+  int jc_fixed_qf = 0;
+  // dual time stepping: physical time step dt and theta (dt = 0: steady),
+  // the time levels Q^n and Q^{n-1}
+  double pt_dt = 0.0, pt_theta = 0.0;
+  std::vector<double> qn, qnm1;
 
   int pc(int i, int j) const { return (j + 1) * (ni + 2) + (i + 1); }
   int ci(int i, int j) const { return j * ni + i; }
@@ -364,6 +371,16 @@ int orc_set_threads(orc_ctx *, int n) {
   return 0;
 }
 
+int orc_set_option(orc_ctx *c, const char *name, double value) {
+  if (!c || !name) return -1;
+  const std::string n(name);
+  if (n == "jc_fixed_qf") {
+    c->jc_fixed_qf = int(value);
+    return 0;
+  }
+  return c->fail(-1, "unknown option " + n);
+}
+
 int orc_set_grid(orc_ctx *c, int ni, int nj, const double *xn, const double *yn, double T_wall,
                  int bc_mode) {
   if (!c || ni < 1 || nj < 1 || !xn || !yn) return -1;
@@ -455,7 +472,34 @@ int orc_prim_to_cons(orc_ctx *c, int n, const double *rho_s, const double *u, co
 int orc_set_state(orc_ctx *c, const double *q) {
   if (!c || !c->has_grid || !c->has_mech || !q) return -1;
   c->q.assign(q, q + size_t(c->m.nv()) * c->N);
+  c->qn = c->q;
+  c->qnm1 = c->q;
   c->has_state = true;
+  c->has_res = false;
+  return 0;
+}
+
+int orc_set_physical_time(orc_ctx *c, double dt, double theta) {
+  if (!c || !(dt >= 0.0) || !(theta >= 0.0)) return -1;
+  c->pt_dt = dt;
+  c->pt_theta = theta;
+  c->has_res = false;
+  return 0;
+}
+
+int orc_set_time_levels(orc_ctx *c, const double *qn, const double *qnm1) {
+  if (!c || !c->has_state || !qn || !qnm1) return -1;
+  const size_t n = size_t(c->m.nv()) * c->N;
+  c->qn.assign(qn, qn + n);
+  c->qnm1.assign(qnm1, qnm1 + n);
+  c->has_res = false;
+  return 0;
+}
+
+int orc_advance_time(orc_ctx *c) {
+  if (!c || !c->has_state) return -1;
+  c->qnm1 = c->qn;
+  c->qn = c->q;
   c->has_res = false;
   return 0;
 }
@@ -649,9 +693,18 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
     double Vp = c->V[p];
     double sv[MAXV];
     source<double>(m, P.q, sv);
+    // physical-time term of dual time stepping (paper Eq. (linearizedimplicit)):
+    // V [(1 + theta)(Q^m - Q^n) - theta (Q^n - Q^{n-1})] / dt joins the residual
+    const bool unsteady = c->pt_dt > 0.0;
     for (int k = 0; k < nv; ++k) {
       c->src[size_t(k) * N + p] = sv[k];
-      c->R[size_t(k) * N + p] = E.F[k] * E.S - W.F[k] * W.S + Nf.F[k] * Nf.S - Sf.F[k] * Sf.S - Vp * sv[k];
+      double Rk = E.F[k] * E.S - W.F[k] * W.S + Nf.F[k] * Nf.S - Sf.F[k] * Sf.S - Vp * sv[k];
+      if (unsteady) {
+        const size_t ix = size_t(k) * N + p;
+        Rk += Vp * ((1.0 + c->pt_theta) * (c->q[ix] - c->qn[ix]) - c->pt_theta * (c->qn[ix] - c->qnm1[ix])) /
+              c->pt_dt;
+      }
+      c->R[size_t(k) * N + p] = Rk;
     }
     const Face *fs4[4] = {&W, &E, &Sf, &Nf};
     double slam = 0.0, sU = 0.0, svF = 0.0, svC = 0.0, svK = 0.0;
@@ -664,9 +717,11 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
     }
     double dt = cfl * Vp / (0.5 * (slam + svK));
     c->dtau[p] = dt;
-    c->dK[p] = Vp / dt + 0.5 * slam + svK;
-    c->dF[p] = Vp / dt + 0.5 * slam + svF;
-    c->dC[p] = Vp / dt + 0.5 * sU + svC;
+    // diagonal: V / dtau, plus (1 + theta) V / dt with physical time
+    const double Vt = Vp / dt + (unsteady ? (1.0 + c->pt_theta) * Vp / c->pt_dt : 0.0);
+    c->dK[p] = Vt + 0.5 * slam + svK;
+    c->dF[p] = Vt + 0.5 * slam + svF;
+    c->dC[p] = Vt + 0.5 * sU + svC;
     // coupled source Jacobian dS/dz (z = rho, momenta, energies, rho_1..rho_{ns-1})
     double z[MAXV];
     q_to_z<double>(m, P.q, z);
@@ -680,14 +735,30 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
       vec_q_to_z<cplx>(m, sc, sz);
       for (int r = 0; r < nb; ++r) c->JK[(size_t(r) * nb + col) * N + p] = sz[r].imag() / h;
     }
-    // species block: d omega_s / d rho_r at fixed T, Tv
+    // species block: d omega_s / d rho_r at fixed T, Tv, or with the flow
+    // variables (momenta, total and vibrational energy) held fixed
     for (int col = 0; col < ns; ++col) {
-      cplx rc[MAXS], om[MAXS];
-      for (int s = 0; s < ns; ++s) rc[s] = P.P.rs[s];
       double h = CSTEP * std::max(std::fabs(P.P.rs[col]), 1.0);
-      rc[col] += cplx(0.0, h);
-      production<cplx>(m, rc, cplx(P.P.T), cplx(P.P.Tv), om);
-      for (int r = 0; r < ns; ++r) c->JC[(size_t(r) * ns + col) * N + p] = om[r].imag() / h;
+      if (c->jc_fixed_qf) {
+        cplx qc[MAXV], sc[MAXV];
+        for (int k = 0; k < nv; ++k) qc[k] = P.q[k];
+        qc[col] += cplx(0.0, h);
+        if (c->jc_fixed_qf == 2) {
+          // velocities and the internal energy density held: the added mass
+          // carries its momentum and kinetic energy
+          qc[ns] += cplx(0.0, h * P.P.u);
+          qc[ns + 1] += cplx(0.0, h * P.P.v);
+          qc[ns + 2] += cplx(0.0, h * 0.5 * (P.P.u * P.P.u + P.P.v * P.P.v));
+        }
+        source<cplx>(m, qc, sc);
+        for (int r = 0; r < ns; ++r) c->JC[(size_t(r) * ns + col) * N + p] = sc[r].imag() / h;
+      } else {
+        cplx rc[MAXS], om[MAXS];
+        for (int s = 0; s < ns; ++s) rc[s] = P.P.rs[s];
+        rc[col] += cplx(0.0, h);
+        production<cplx>(m, rc, cplx(P.P.T), cplx(P.P.Tv), om);
+        for (int r = 0; r < ns; ++r) c->JC[(size_t(r) * ns + col) * N + p] = om[r].imag() / h;
+      }
     }
     // flow block source row (two temperatures): d omega_ve / d Q_F at frozen Y
     if (m.two_temp) {

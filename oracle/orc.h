@@ -53,6 +53,15 @@ int orc_create(orc_ctx **ctx);
 void orc_destroy(orc_ctx *ctx);
 const char *orc_last_error(const orc_ctx *ctx);
 int orc_set_threads(orc_ctx *ctx, int n);
+/* named options: "jc_fixed_qf" (0: split species block at fixed T, Tv;
+ * 1: at fixed momenta and energies, the temperatures following) */
+int orc_set_option(orc_ctx *ctx, const char *name, double value);
+/* dual time stepping (paper Section 2.2, Eq. (linearizedimplicit)): physical
+ * step dt (0: steady) and theta; orc_advance_time: Q^{n-1} <- Q^n <- Q
+ * (orc_set_state sets both levels to the state) */
+int orc_set_physical_time(orc_ctx *ctx, double dt, double theta);
+int orc_advance_time(orc_ctx *ctx);
+int orc_set_time_levels(orc_ctx *ctx, const double *qn, const double *qnm1);
 
 /* nodes [(nj+1)][(ni+1)]; bc_mode 0: wall at j=0, far field at j=nj, outflow at i=0,ni;
  * bc_mode 1: free-stream Dirichlet on all four sides (free-stream preservation test). */

@@ -89,6 +89,20 @@ class Oracle:
             msg = self.L.orc_last_error(self.ctx).decode() if getattr(self, "ctx", None) else ""
             raise RuntimeError(f"oracle error {rc}: {msg}")
 
+    def set_physical_time(self, dt, theta=0.0):
+        self._check(self.L.orc_set_physical_time(self.ctx, C.c_double(dt), C.c_double(theta)))
+
+    def set_time_levels(self, qn, qnm1):
+        a, pa = _d(qn)
+        b, pb = _d(qnm1)
+        self._check(self.L.orc_set_time_levels(self.ctx, pa, pb))
+
+    def advance_time(self):
+        self._check(self.L.orc_advance_time(self.ctx))
+
+    def set_option(self, name, value):
+        self._check(self.L.orc_set_option(self.ctx, name.encode(), C.c_double(value)))
+
     # ---------------------------------------------------------------- setup
     def set_grid(self, x, y, T_wall=300.0, bc_mode=0):
         nj1, ni1 = x.shape

@@ -31,8 +31,10 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_get_cells",
             "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times",
             "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
-            "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate"]
-PHASES = ["prim", "faces", "cell", "norms", "sweep_fwd", "sweep_bwd", "update"]
+            "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate",
+            "csi_set_species_jacobian", "csi_set_physical_time", "csi_advance_time",
+            "csi_set_time_levels"]
+PHASES = ["prim", "faces", "cell", "block", "norms", "sweep_fwd", "sweep_bwd", "update"]
 
 
 class CsiError(RuntimeError):
@@ -284,6 +286,26 @@ class Solver:
         self._check(self.L.csi_sample_jacobians(self.ctx, ms, C.c_void_p(x_raw.data_ptr()),
                                                 C.c_void_p(jc.data_ptr()), C.byref(n)))
         return n.value
+
+    def set_physical_time(self, dt, theta=0.0):
+        """Dual time stepping: physical step dt (0: steady) and theta (0 backward
+        Euler, 0.5 second-order backward difference)."""
+        self._check(self.L.csi_set_physical_time(self.ctx, C.c_double(dt), C.c_double(theta)))
+
+    def advance_time(self):
+        """Q^{n-1} <- Q^n <- Q: start the next physical time step."""
+        self._check(self.L.csi_advance_time(self.ctx))
+
+    def set_time_levels(self, qn, qnm1):
+        """Time levels Q^n, Q^{n-1} (host float64 [nv][N] each)."""
+        a, pa = _d(qn)
+        b, pb = _d(qnm1)
+        self._check(self.L.csi_set_time_levels(self.ctx, pa, pb, 0))
+
+    def set_species_jacobian(self, reading):
+        """0: split species block at fixed T, Tv; 1: at fixed velocities and
+        internal energy densities (temperatures follow the composition)."""
+        self._check(self.L.csi_set_species_jacobian(self.ctx, int(reading)))
 
     def set_surrogate(self, params, scales, stall_ratio=0.98, stall_window=100):
         """Install a network: params float32 cuda tensor, scales (mu, sigma, tau0) host."""

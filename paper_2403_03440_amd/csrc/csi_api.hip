@@ -79,7 +79,15 @@ struct csi_ctx {
   int trace = 0;                     // per-strip sweep trace (csi_set_timing(ctx, 2))
   long long *trace_buf = nullptr;
   std::vector<hipEvent_t> ev;
-  double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double phase_ms[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+  // split species block: 0 = J_C at fixed T, Tv; 1 = at fixed velocities,
+  // internal and vibrational energy densities (cell kernel flag bit 3)
+  int jc_reading = 0;
+  // physical time (dual time stepping): the unsteady terms carry
+  // pt_a = (1 + theta) / dt and pt_b = theta / dt (both 0: steady)
+  double pt_a = 0.0, pt_b = 0.0;
+  int jc_flag() const { return jc_reading ? 8 : 0; }
 
   int nv() const { return ns + 3 + (nt == 2 ? 1 : 0); }
   int nf() const { return nt == 2 ? 5 : 4; }
@@ -166,6 +174,7 @@ Layout layout(const csi_ctx *c, int nprim) {
       size_t(4) * c->ni * TR_N * 8,                   // 46 sweep trace
       size_t(c->ns >= BLOCK_NS_MIN ? hb_fields(c->ns, nv) : 2) * N * 8,  // 47 cell kernel -> block kernel hand-off
       size_t(nv) * N * 8,                             // 48 state at the start of csi_step (surrogate divergence fallback)
+      size_t(nv) * N * 8, size_t(nv) * N * 8,         // 49-50 physical-time levels Q^n, Q^{n-1}
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -283,6 +292,7 @@ int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
   c->nt = mm->two_temp ? 2 : 1;
   c->group_c = 1;  // persistent group kernels
   c->has_mech = true;
+  c->jc_reading = 0;
   c->has_fs = false;
   c->bound = false;
   c->has_state = false;
@@ -347,6 +357,10 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   c->trace_buf = reinterpret_cast<long long *>(b + L.off[46]);
   w.diag = D(47);
   w.qbak = D(48);
+  w.qn = D(49);
+  w.qnm1 = D(50);
+  w.pt_a = c->pt_a;
+  w.pt_b = c->pt_b;
   w.trace = c->trace > 0 ? c->trace_buf : nullptr;
   c->has_sur = false;
   w.group_c = c->group_c;
@@ -392,13 +406,59 @@ int csi_set_state(csi_ctx *c, const double *q, int on_device) {
   int rc = hip_check(c, hipMemcpyAsync(c->w.Q, q, n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                        c->stream), "set_state");
   if (rc) return rc;
-  rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+  // the physical-time levels start at the state (no unsteady term until csi_advance_time)
+  const size_t qb = size_t(c->nv()) * c->N * 8;
+  hipError_t e = hipMemcpyAsync(c->w.qn, c->w.Q, qb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->w.qnm1, c->w.Q, qb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  rc = hip_check(c, e, "set_state");
   if (rc) return rc;
   c->has_state = true;
   c->has_res = false;
   c->has_dq = false;
   c->prim_warm = false;  // results depend only on the state and the calls since it was set
   c->it_global = 0;
+  return reset_flags(c);
+}
+
+int csi_set_physical_time(csi_ctx *c, double dt, double theta) {
+  if (!c) return CSI_ERR_ARG;
+  if (!(dt >= 0.0) || !(theta >= 0.0) || !std::isfinite(dt) || !std::isfinite(theta))
+    return c->fail(CSI_ERR_ARG, "set_physical_time: dt and theta must be finite and >= 0");
+  c->pt_a = dt > 0.0 ? (1.0 + theta) / dt : 0.0;
+  c->pt_b = dt > 0.0 ? theta / dt : 0.0;
+  c->w.pt_a = c->pt_a;
+  c->w.pt_b = c->pt_b;
+  c->has_res = false;
+  c->has_dq = false;
+  return CSI_OK;
+}
+
+int csi_set_time_levels(csi_ctx *c, const double *qn, const double *qnm1, int on_device) {
+  if (!c || !qn || !qnm1) return CSI_ERR_ARG;
+  if (!ready(c)) return c->fail(CSI_ERR_STATE, "set_time_levels: workspace/state not set");
+  const size_t qb = size_t(c->nv()) * c->N * 8;
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t e = hipMemcpyAsync(c->w.qn, qn, qb, k, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->w.qnm1, qnm1, qb, k, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->has_res = false;
+  c->has_dq = false;
+  return hip_check(c, e, "set_time_levels");
+}
+
+int csi_advance_time(csi_ctx *c) {
+  if (!c) return CSI_ERR_ARG;
+  if (!ready(c)) return c->fail(CSI_ERR_STATE, "advance_time: workspace/state not set");
+  const size_t qb = size_t(c->nv()) * c->N * 8;
+  hipError_t e = hipMemcpyAsync(c->w.qnm1, c->w.qn, qb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->w.qn, c->w.Q, qb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  int rc = hip_check(c, e, "advance_time");
+  if (rc) return rc;
+  c->has_res = false;
+  c->has_dq = false;
+  c->it_global = 0;  // the next csi_step starts its residual drop and CFL ramp afresh
   return reset_flags(c);
 }
 
@@ -446,7 +506,7 @@ int csi_implicit_op(csi_ctx *c, int mode, int precision, int jac) {
   if (!ready(c) || !c->has_res) return c->fail(CSI_ERR_STATE, "implicit_op before residual");
   hipError_t e = hipSuccess;
   if (jac == CSI_JAC_SURROGATE) e = c->run->surrogate(c->g, c->w, c->stream, false);
-  if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, 0.0, mode, precision, jac == CSI_JAC_SURROGATE ? 6 : 2, false);
+  if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, 0.0, mode, precision, (jac == CSI_JAC_SURROGATE ? 6 : 2) | c->jc_flag(), false);
   if (e == hipSuccess) e = c->run->sweeps(c->g, c->w, c->stream, mode, precision, false);
   int rc = hip_check(c, e, "implicit_op launch");
   if (rc) return rc;
@@ -478,8 +538,9 @@ int csi_consistency_correct(csi_ctx *c, int kind) {
   return CSI_OK;
 }
 
-// events per timed iteration: boundaries of prim, faces, cell, norms, forward sweep, backward sweep, update
-static constexpr int NEV = 8;
+// events per timed iteration: boundaries of prim, faces, cell, block, norms, forward sweep, backward sweep,
+// update
+static constexpr int NEV = 9;
 
 int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   if (!c || !p) return CSI_ERR_ARG;
@@ -553,15 +614,16 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
     if (e == hipSuccess) e = c->run->faces(c->g, c->w, c->stream, true);
     if (E && e == hipSuccess) e = hipEventRecord(E[2], c->stream);
     if (e == hipSuccess)
-      e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, sur ? 7 : 3, true, sur ? c->ev_sur : nullptr);
-    if (E && e == hipSuccess) e = hipEventRecord(E[3], c->stream);
+      e = c->run->cell(c->g, c->w, c->stream, cfl, p->mode, p->precision, (sur ? 7 : 3) | c->jc_flag(), true,
+                         sur ? c->ev_sur : nullptr, E ? E[3] : nullptr);
+    if (E && e == hipSuccess) e = hipEventRecord(E[4], c->stream);
     const StallArgs stall{sur ? c->w.flags + FL_SURR_OFF : nullptr, int(it_start), c->sur_window, c->sur_ratio};
     if (e == hipSuccess) e = c->run->norms(c->w, c->stream, int(m), p->tol, true, stall);
-    if (E && e == hipSuccess) e = hipEventRecord(E[4], c->stream);
-    if (e == hipSuccess) e = c->run->sweeps(c->g, c->w, c->stream, p->mode, p->precision, true, E ? E[5] : nullptr);
-    if (E && e == hipSuccess) e = hipEventRecord(E[6], c->stream);
-    if (e == hipSuccess) e = c->run->update(c->g, c->w, c->stream, p->mode, p->precision, p->kind, true);
+    if (E && e == hipSuccess) e = hipEventRecord(E[5], c->stream);
+    if (e == hipSuccess) e = c->run->sweeps(c->g, c->w, c->stream, p->mode, p->precision, true, E ? E[6] : nullptr);
     if (E && e == hipSuccess) e = hipEventRecord(E[7], c->stream);
+    if (e == hipSuccess) e = c->run->update(c->g, c->w, c->stream, p->mode, p->precision, p->kind, true);
+    if (E && e == hipSuccess) e = hipEventRecord(E[8], c->stream);
     if ((rc = hip_check(c, e, "step launch"))) return rc;
     c->it_global++;
     st.iters = it + 1;
@@ -583,12 +645,14 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
         return c->fail(CSI_ERR_HIP, "step: a sweep wave timed out waiting for its neighbour strip");
       }
       if ((fl[FL_BAD] != INT_MAX || fl[FL_SING] != INT_MAX) && guard && fl[FL_SURR_OFF] < 0 && !fl[FL_ABORT]) {
-        const int clean[1] = {INT_MAX};
+        // every flag and counter starts afresh (the discarded iterations'
+        // clip and dominance-fallback counts and a stop flag must not carry
+        // over), then the surrogate is off from the call's first iteration
         const int off = int(bak_global);
         hipError_t e2 = hipMemcpyAsync(c->w.Q, c->w.qbak, qbytes, hipMemcpyDeviceToDevice, c->stream);
-        if (e2 == hipSuccess) e2 = hipMemcpyAsync(c->w.flags + FL_BAD, clean, sizeof(int), hipMemcpyHostToDevice, c->stream);
-        if (e2 == hipSuccess) e2 = hipMemcpyAsync(c->w.flags + FL_SING, clean, sizeof(int), hipMemcpyHostToDevice, c->stream);
-        if (e2 == hipSuccess) e2 = hipMemcpyAsync(c->w.flags + FL_SURR_OFF, &off, sizeof(int), hipMemcpyHostToDevice, c->stream);
+        if ((rc = hip_check(c, e2, "divergence fallback"))) return rc;
+        if ((rc = reset_flags(c))) return rc;
+        e2 = hipMemcpyAsync(c->w.flags + FL_SURR_OFF, &off, sizeof(int), hipMemcpyHostToDevice, c->stream);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
         if ((rc = hip_check(c, e2, "divergence fallback"))) return rc;
         c->it_global = bak_global;
@@ -630,6 +694,17 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   st.r_last = nrm[0];
   if (s) *s = st;
   c->has_res = false;
+  c->has_dq = false;
+  return CSI_OK;
+}
+
+int csi_set_species_jacobian(csi_ctx *c, int reading) {
+  if (!c) return CSI_ERR_ARG;
+  if (reading != 0 && reading != 1) return c->fail(CSI_ERR_ARG, "set_species_jacobian: reading must be 0 or 1");
+  if (!c->has_mech) return c->fail(CSI_ERR_STATE, "set_species_jacobian before set_mechanism");
+  if (reading == 1 && c->ns < BLOCK_NS_MIN)
+    return c->fail(CSI_ERR_UNSUPPORTED, "set_species_jacobian: reading 1 needs ns >= " + std::to_string(BLOCK_NS_MIN));
+  c->jc_reading = reading;
   c->has_dq = false;
   return CSI_OK;
 }
@@ -1035,6 +1110,20 @@ int csi_mlp_prepare(csi_ctx *c, int n, int n_in, int n_out, const float *x_raw, 
   return hip_check(c, hipStreamSynchronize(st), "sync");
 }
 
+// pack the operands into `packed` (d.nslots 16-byte slots), then the forward pass
+hipError_t mlp_forward_launch(const MlpDims &d, const float *params, const float *x, int n, float *y, void *packed,
+                              hipStream_t st) {
+  hipError_t e = mlp_pack(d, params, packed, st);
+  auto *P = static_cast<const u16x8 *>(packed);
+  const unsigned nb = unsigned((long(n) + 63) / 64);
+  if (e == hipSuccess) {
+    if (d.ks1 == 1) hipLaunchKernelGGL(k_mlp_forward<1>, dim3(nb), dim3(256), 0, st, d, P, params, x, n, y);
+    else hipLaunchKernelGGL(k_mlp_forward<2>, dim3(nb), dim3(256), 0, st, d, P, params, x, n, y);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 int csi_mlp_forward(csi_ctx *c, int n_in, int n_out, int n, const float *params, const float *x, float *y, void *work,
                     size_t work_bytes) {
   if (!c) return CSI_ERR_ARG;
@@ -1044,15 +1133,7 @@ int csi_mlp_forward(csi_ctx *c, int n_in, int n_out, int n, const float *params,
   if (rc) return rc;
   char *w = static_cast<char *>(work);
   const MlpWork W = mlp_work(d, 1);
-  hipError_t e = mlp_pack(d, params, w + W.off[0], c->stream);
-  auto *P = reinterpret_cast<const u16x8 *>(w + W.off[0]);
-  const unsigned nb = unsigned((long(n) + 63) / 64);
-  if (e == hipSuccess) {
-    if (d.ks1 == 1) hipLaunchKernelGGL(k_mlp_forward<1>, dim3(nb), dim3(256), 0, c->stream, d, P, params, x, n, y);
-    else hipLaunchKernelGGL(k_mlp_forward<2>, dim3(nb), dim3(256), 0, c->stream, d, P, params, x, n, y);
-    e = hipGetLastError();
-  }
-  return hip_check(c, e, "mlp_forward launch");
+  return hip_check(c, mlp_forward_launch(d, params, x, n, y, w + W.off[0], c->stream), "mlp_forward launch");
 }
 
 int csi_mlp_grad(csi_ctx *c, const csi_mlp_batch *b, float *grad, double *loss) {

@@ -449,9 +449,22 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     }
   } else {
     const double dF = d0, dC = d1;
+    // flags bit 3: the species block with the velocities and the internal
+    // (and vibrational) energy densities held, so that the temperatures follow
+    // the composition: J_C += d omega_t/dT dT/d rho_c (+ the Tv term), the
+    // temperature derivatives taken along the direction that adds mass at the
+    // cell's velocity and kinetic energy
+    const bool te = (flags & 8) != 0 && !use_sur;
+    const double uu = prim[F_U * NP + pc], vv = prim[F_V * NP + pc], ke = 0.5 * (uu * uu + vv * vv);
 #pragma unroll
-    for (int c = 0; c < NS; ++c)
-      A[c] = (c == k ? dC : 0.0) - Vp * (use_sur ? double(out.Jsur[size_t(tc * NS + c) * g.N + p]) : row[c]);
+    for (int c = 0; c < NS; ++c) {
+      double jc = use_sur ? double(out.Jsur[size_t(tc * NS + c) * g.N + p]) : row[c];
+      if (te) {
+        jc += dwT * (TQ[c] + uu * TQ[NS] + vv * TQ[NS + 1] + ke * TQ[NS + 2]);
+        if (NT == 2) jc += dwTv * (TQ[NV + c] + uu * TQ[NV + NS] + vv * TQ[NV + NS + 1] + ke * TQ[NV + NS + 2]);
+      }
+      A[c] = (c == k ? dC : 0.0) - Vp * jc;
+    }
     // flow block: diagonal 1/dF, and in two temperatures the rho e_ve row
     // -V d omega_ve / d Q_F (frozen Y) eliminated in closed form
     double df6[6] = {1.0 / dF, 0.0, 0.0, 0.0, 0.0, 0.0};

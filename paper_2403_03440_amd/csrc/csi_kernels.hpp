@@ -486,6 +486,10 @@ struct CellOut {
   const float *Jsur;           // surrogate J_C [ns * ns][N] (flags bit 4)
   unsigned long long *ddfail;  // count of cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off (stall), use the exact block
+  // dual time stepping: physical-time levels and pt_a = (1 + theta) / dt,
+  // pt_b = theta / dt (pt_a = 0: steady)
+  const double *qn, *qnm1;
+  double pt_a, pt_b;
 };
 
 template <int NS, int NT, typename RT>
@@ -533,6 +537,12 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         double sv = k < NS ? C.w[k] : (NT == 2 && k == NS + 3 ? C.wv : 0.0);
         R[k] = Fi[size_t(k) * nfi + fE] * SE - Fi[size_t(k) * nfi + fW] * SW + Fj[size_t(k) * nfj + fN] * SN -
                Fj[size_t(k) * nfj + fS] * SS - Vp * sv;
+        // dual time stepping (Section 2.2): the unsteady residual adds
+        // V [(1 + theta)(Q - Q^n) - theta (Q^n - Q^{n-1})] / dt
+        if (out.pt_a != 0.0) {
+          const double qnk = out.qn[size_t(k) * g.N + p], qmk = out.qnm1[size_t(k) * g.N + p];
+          R[k] += Vp * (out.pt_a * (q[k] - qnk) - out.pt_b * (qnk - qmk));
+        }
         out.R[size_t(k) * g.N + p] = R[k];
         if (out.src) out.src[size_t(k) * g.N + p] = sv;
       } else {
@@ -583,7 +593,8 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         hb[size_t(NS + NV + c) * g.N] = dTv;
       }
     }
-    double Vdt = Vp / dt;
+    // pseudo-time and physical-time diagonal: V / dtau + (1 + theta) V / dt
+    double Vdt = Vp / dt + Vp * out.pt_a;
     // hyperplane schedule: cell-major records (field f at f N + p)
     const bool grp = out.group_c > 0;
     RT *bb = reinterpret_cast<RT *>(out.b);

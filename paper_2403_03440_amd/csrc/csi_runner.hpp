@@ -18,6 +18,8 @@ struct WS {
   long long *trace;           // optional per-strip sweep trace [fwd, bwd][part][ni][TR_N] (null: off)
   double *diag;               // [hb_fields][N] per-cell hand-off from k_cell to k_block
   double *qbak;               // [nv][N] state at the start of csi_step (surrogate divergence fallback)
+  double *qn, *qnm1;          // [nv][N] physical-time levels Q^n, Q^{n-1} (dual time stepping)
+  double pt_a, pt_b;          // (1 + theta) / dt and theta / dt (0: steady)
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
   int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels
@@ -40,8 +42,10 @@ class IRunner {
   virtual hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
   // sur_ready (optional): event after which the surrogate's blocks are in
   // place; the launch makes the first kernel that reads them wait for it
+  // mid (optional): recorded between the cell kernel and the block kernel
+  // (right after the cell kernel where there is no block kernel)
   virtual hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
-                          bool stoppable, hipEvent_t sur_ready = nullptr) = 0;
+                          bool stoppable, hipEvent_t sur_ready = nullptr, hipEvent_t mid = nullptr) = 0;
   virtual hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable,
                            StallArgs stall = StallArgs{nullptr, 0, 0, 0.0}) = 0;
   virtual hipError_t surrogate(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
@@ -85,7 +89,7 @@ template <int NS, int NT> class Runner : public IRunner {
   }
 
   hipError_t cell(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int prec, int flags,
-                  bool stoppable, hipEvent_t sur_ready = nullptr) override {
+                  bool stoppable, hipEvent_t sur_ready = nullptr, hipEvent_t mid = nullptr) override {
     // with the diagonal blocks built by k_block only that kernel reads the
     // surrogate's blocks, so the cell kernel runs beside the inference
     const bool blk = NS >= BLOCK_NS_MIN && (flags & 2);
@@ -94,7 +98,7 @@ template <int NS, int NT> class Runner : public IRunner {
       if (e != hipSuccess) return e;
     }
     CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].S, w.grp[1].S}, w.src, w.flags + FL_SING, w.group_c,
-              w.diag, w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF};
+              w.diag, w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF, w.qn, w.qnm1, w.pt_a, w.pt_b};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
     if (prec == 0)
       hipLaunchKernelGGL((k_cell<NS, NT, double>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
@@ -102,6 +106,10 @@ template <int NS, int NT> class Runner : public IRunner {
     else
       hipLaunchKernelGGL((k_cell<NS, NT, float>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
                          w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    if (mid) {
+      const hipError_t e = hipEventRecord(mid, st);
+      if (e != hipSuccess) return e;
+    }
     if constexpr (NS >= BLOCK_NS_MIN) {
       if (flags & 2) {
         const BlockOut bo{{w.grp[0].S, w.grp[1].S}, w.Dinv, w.group_c, w.diag, w.sur.J, ddfail_counter(w.flags),

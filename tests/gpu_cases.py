@@ -36,24 +36,39 @@ def freestream(mech, u=5000.0, T=250.0, rho=1e-3):
     return (rho * Y, u, 0.0, T, T)
 
 
-def oracle_noise(o, q0, mode, cfl, groups, n=3, eps=4e-16, seed=0):
+def oracle_noise(o, q0, mode, cfl, groups, n=3, eps=4e-16, seed=0, levels=None):
     """Sensitivity of the oracle's own increment to rounding-level relative
-    perturbations of its input state: the noise floor of the comparison."""
+    perturbations of its input state: the noise floor of the comparison.
+    levels: physical-time levels (Q^n, Q^{n-1}) to restore after each
+    set_state (dual time stepping)."""
     rng = np.random.default_rng(seed)
-    o.set_state(q0)
+
+    def put(q):
+        o.set_state(q)
+        if levels is not None:
+            o.set_time_levels(*levels)
+
+    put(q0)
     o.residual(cfl)
     o.implicit_op(mode)
     d0 = o.get("dq", mode)
     worst = np.zeros(d0.shape[0])
     for _ in range(n):
-        o.set_state(q0 * (1.0 + eps * rng.uniform(-1.0, 1.0, q0.shape)))
+        put(q0 * (1.0 + eps * rng.uniform(-1.0, 1.0, q0.shape)))
         o.residual(cfl)
         o.implicit_op(mode)
         worst = np.maximum(worst, normwise(o.get("dq", mode), d0, groups))
-    o.set_state(q0)
+    put(q0)
     o.residual(cfl)
     o.implicit_op(mode)
     return worst
+
+
+def make_pair_evolved(name, ni, nj, iters=40):
+    """(mechanism, oracle, HIP solver, state) on an oracle-evolved state."""
+    m = mech_by_name(name)
+    o, s, q0 = pair(m, ni, nj, state="evolved", mech_name=name, iters=iters)
+    return m, o, s, q0
 
 
 _EVOLVED = {}

@@ -1,0 +1,87 @@
+"""GPU parity of dual time stepping (paper Section 2.2, Eq. (dualimplicit),
+Eq. (linearizedimplicit)) against the oracle: the unsteady residual and the
+increments with the physical-time diagonal, for given time levels Q^n and
+Q^{n-1}; a short physical-time run of both from the same state; argument
+errors."""
+import numpy as np
+import pytest
+
+from gpu_cases import groups_inc, groups_state, make_pair_evolved, normwise, oracle_noise
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _csi():
+    from paper_2403_03440_amd import csi
+    return csi
+
+
+def _levels(q0, seed):
+    from paper_2403_03440_amd import inputs as I
+    n = q0.size
+    qn = q0 * (1.0 + 2e-3 * I.uniform_pm1(seed, n).reshape(q0.shape))
+    qm = q0 * (1.0 + 4e-3 * I.uniform_pm1(seed + 1, n).reshape(q0.shape))
+    return qn, qm
+
+
+@pytest.mark.parametrize("name", ["air5_1T", "air5_2T", "air11_2T", "syn20_1T"])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("theta", [0.0, 0.5])
+def test_dual_time_increment_parity(name, mode, theta):
+    print(f"case {name} 32x24 mode {mode} theta {theta}", flush=True)
+    csi = _csi()
+    m, o, s, q0 = make_pair_evolved(name, 32, 24)
+    qn, qm = _levels(q0, 17)
+    dt = 2e-6
+    for x in (o, s):
+        x.set_physical_time(dt, theta)
+        x.set_time_levels(qn, qm)
+    g = groups_inc(m, mode)
+    noise = oracle_noise(o, q0, mode, 10.0, g, levels=(qn, qm))
+    o.residual(10.0)
+    s.residual(10.0)
+    assert np.all(normwise(s.get("R"), o.get("R"), groups_state(m)) <= TOL64 * 10)
+    o.implicit_op(mode)
+    s.implicit_op(mode, csi.FP64)
+    e = normwise(s.get("dq", mode), o.get("dq", mode), g)
+    tol = np.maximum(TOL64, 10.0 * noise)
+    print("err", e.max(), "tol", tol.max(), flush=True)
+    assert np.all(tol <= 1e-9)
+    assert np.all(e <= tol), (e, tol)
+    s.implicit_op(mode, csi.MIXED)
+    assert np.all(normwise(s.get("dq", mode), o.get("dq", mode), g) <= 2e-5)
+    for x in (o, s):
+        x.set_physical_time(0.0, 0.0)
+
+
+def test_dual_time_short_run():
+    """Three physical steps (theta 0, then 1/2), 30 pseudo-time iterations
+    each, GPU split mixed against the oracle's split FP64: the states agree to
+    the pseudo-time residual level."""
+    csi = _csi()
+    m, o, s, q0 = make_pair_evolved("air5_2T", 32, 24)
+    for x in (o, s):
+        x.set_state(q0)
+    for n in range(3):
+        theta = 0.0 if n == 0 else 0.5
+        o.set_physical_time(2e-6, theta)
+        s.set_physical_time(2e-6, theta)
+        o.advance_time()
+        s.advance_time()
+        h = o.step(1, 2, 1e3, 30, ramp=0, it0=0)
+        st = s.step(csi.SPLIT, csi.CC2, 1e3, 30, precision=csi.MIXED, cfl_ramp=0, check_every=30)
+        print(f"step {n}: oracle drop {h[-1, 0] / h[0, 0]:.2e}, gpu iterations {st['iters']}", flush=True)
+    e = normwise(s.get_state(), o.get_state(), groups_state(m))
+    print("state err", e.max(), flush=True)
+    assert np.all(e <= 1e-8)
+
+
+def test_dual_time_argument_errors():
+    csi = _csi()
+    m, o, s, q0 = make_pair_evolved("air5_1T", 8, 6)
+    with pytest.raises(csi.CsiError, match="CSI_ERR_ARG"):
+        s.set_physical_time(-1.0, 0.0)
+    with pytest.raises(csi.CsiError, match="CSI_ERR_ARG"):
+        s.set_physical_time(1e-6, float("nan"))

@@ -381,16 +381,31 @@ def test_trained_surrogate_reaches_the_same_steady_state():
     print("training", hist[0], hist[-1])
     assert hist[-1][1] < 0.5 * hist[0][1]
     res = {}
+    import time
+    import torch
     for jac in (csi.JAC_EXACT, csi.JAC_SURROGATE):
         s.set_state(q0)
         if jac == csi.JAC_SURROGATE:
             s.set_surrogate(params, scales)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         st = s.step(csi.SPLIT, csi.CC2, cfg.cfl, 8000, precision=csi.MIXED, jac=jac, cfl_ramp=100, tol=1e-10,
                     check_every=50)
-        res[jac] = (st, s.get_state(), s.wall_heat_flux()[1])
+        torch.cuda.synchronize()
+        res[jac] = (st, s.get_state(), s.wall_heat_flux()[1], time.perf_counter() - t0)
         print("jac", jac, "iterations", st["iters"], "converged", st["converged"], "dd fallbacks",
-              st["n_dd_fallback"], "off at", st["surrogate_off_at"])
-    (se, qe, qse), (ss, qs, qss) = res[csi.JAC_EXACT], res[csi.JAC_SURROGATE]
+              st["n_dd_fallback"], "off at", st["surrogate_off_at"], f"{res[jac][3]:.3f} s")
+    (se, qe, qse, te), (ss, qs, qss, ts) = res[csi.JAC_EXACT], res[csi.JAC_SURROGATE]
+    # what the network gains or loses: iterations and solve time against the
+    # exact block, and the training time
+    print(f"surrogate: {ss['iters'] - se['iters']:+d} iterations, solve {ts - te:+.3f} s, "
+          f"training {hist[-1][3]:.3f} s", flush=True)
     assert se["converged"] and ss["converged"]
+    # the network was in use: no stall or divergence fallback, and its block
+    # passed the dominance check in part of the cell-iterations (about 13 % for
+    # 11-species air on this grid, where in molar units about a third of the
+    # exact blocks pass it)
+    assert ss["surrogate_off_at"] == -1 and ss["surrogate_diverged"] == 0
+    assert ss["n_dd_fallback"] <= 0.95 * ss["iters"] * s.N
     assert normwise(qs, qe, [list(range(m.ns)), [m.ns, m.ns + 1], [m.ns + 2], [m.ns + 3]]).max() <= 1e-6
     assert abs(qss - qse) <= 1e-6 * abs(qse)

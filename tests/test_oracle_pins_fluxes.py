@@ -439,3 +439,54 @@ def test_cc1_weights_are_mass_fractions(kind):
     assert np.abs(rho1 / (rho0 + dq[0]) - 1.0).max() <= 4e-16
     assert np.abs(q1[:m.ns] / rho1 - q0[:m.ns] / rho0).max() <= 4e-16
     assert np.abs(dq[0] / rho0).max() > 1e-4    # the density did change
+
+
+# ------------------------------------ species block at fixed internal energy
+@pytest.mark.parametrize("name", ["air5_1T", "syn20_1T", "air5_2T"])
+def test_species_jacobian_fixed_internal_energy(name):
+    """The split species block's second reading (velocities and the internal
+    and vibrational energy densities held, the temperatures following the
+    composition) equals the fixed-temperature Jacobian plus the chain rule
+    through the energies, written out here: dT/d rho_r = -(e_r - e_ve,r) /
+    (rho c_v,tr) and dTv/d rho_r = -e_ve,r / (rho c_v,ve) in two temperatures,
+    dT/d rho_r = -e_r / (rho c_v) in one; every derivative of the production
+    rates by central differences of the point rates."""
+    m = {"air5_1T": lambda: I.air5(0), "syn20_1T": lambda: I.synthetic(20, 60, 3442),
+         "air5_2T": lambda: I.air5(1)}[name]()
+    x, y = I.polar_grid(4, 3)
+    Y = np.zeros(m.ns)
+    Y[m.ns - 1], Y[0] = 0.767, 0.233
+    o = orc.setup((x, y), m, (1e-3 * Y, 5000.0, 0.0, 250.0, 250.0))
+    q = o.prim_to_cons(*I.random_prims(m, 12, 11, T_range=(2500.0, 7000.0), speed=3000.0, y_floor=0.01))
+    o.set_state(q)
+    o.set_option("jc_fixed_qf", 2)
+    o.residual(10.0)
+    JC = o.get("JC")
+    T, Tv = o.get("T"), o.get("Tv")
+    ns = m.ns
+    for p in (0, 5, 11):
+        rs = q[:ns, p].copy()
+        Tp, Tvp = T[p], Tv[p] if m.two_temp else T[p]
+        om = lambda r, t, tv: o.point_production(r, t, tv)[0]
+        JT = np.zeros((ns, ns))
+        for r in range(ns):
+            h = 1e-6 * rs[r]
+            dp, dm = rs.copy(), rs.copy()
+            dp[r] += h
+            dm[r] -= h
+            JT[:, r] = (om(dp, Tp, Tvp) - om(dm, Tp, Tvp)) / (2 * h)
+        dwdT = (om(rs, Tp * (1 + 1e-7), Tvp) - om(rs, Tp * (1 - 1e-7), Tvp)) / (2e-7 * Tp)
+        e, _, cv, _ = o.point_thermo(Tp, Tvp)
+        if m.two_temp:
+            e0, _, cv0, _ = o.point_thermo(Tp, 1e-3)     # no vibrational energy at Tv -> 0
+            eve, cvve = e - e0, cv - cv0
+            dT = -(e - eve) / (rs @ cv0)
+            dTv = -eve / (rs @ cvve)
+            dwdTv = (om(rs, Tp, Tvp * (1 + 1e-7)) - om(rs, Tp, Tvp * (1 - 1e-7))) / (2e-7 * Tvp)
+            J = JT + np.outer(dwdT, dT) + np.outer(dwdTv, dTv)
+        else:
+            J = JT + np.outer(dwdT, -e / (rs @ cv))
+        err = np.abs(JC[:, :, p] - J).max() / np.abs(J).max()
+        assert err <= 2e-6, (p, err)
+        # and the temperature term is not negligible here
+        assert np.abs(J - JT).max() >= 1e-3 * np.abs(J).max()
