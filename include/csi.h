@@ -270,6 +270,22 @@ int csi_mlp_prepare(csi_ctx *ctx, int n, int n_in, int n_out, const float *x_raw
 int csi_mlp_forward(csi_ctx *ctx, int n_in, int n_out, int n, const float *params, const float *x, float *y,
                     void *work, size_t work_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * csi_mlp_forward without the work argument.  The packed BF16 operands go to
+ * a library-owned device array of CSI_MLP_NOALLOC_SCRATCH_BYTES, one per GPU,
+ * held until the process ends; its address is taken at csi_create on that
+ * context's device.  The call allocates nothing and launches the same kernels
+ * as csi_mlp_forward on the context's stream (asynchronous).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other contexts, other host threads) race and must be serialised
+ * by the caller.  Every network within the limits above (n_in <= 64,
+ * n_out <= 1024: at most 286 720 bytes of packed operands) fits; a larger
+ * packed size returns CSI_ERR_ARG.  Other errors as csi_mlp_forward. */
+#define CSI_MLP_NOALLOC_SCRATCH_BYTES 327680
+int csi_mlp_forward_noalloc(csi_ctx *ctx, int n_in, int n_out, int n, const float *params, const float *x,
+                            float *y);
+
 typedef struct {
   int n_in, n_out;
   int n_data;        /* rows of x and t */

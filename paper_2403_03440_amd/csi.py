@@ -31,7 +31,7 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_get_cells",
             "csi_norm_history", "csi_get_array", "csi_prim_to_cons", "csi_set_timing", "csi_phase_times",
             "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
-            "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate",
+            "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate", "csi_mlp_forward_noalloc",
             "csi_set_species_jacobian", "csi_set_physical_time", "csi_advance_time",
             "csi_set_time_levels"]
 PHASES = ["prim", "faces", "cell", "block", "norms", "sweep_fwd", "sweep_bwd", "update"]
@@ -373,6 +373,14 @@ class Mlp:
         y = self.torch.empty((x.shape[0], self.n_out), dtype=self.torch.float32, device=self.dev)
         self._check(self.L.csi_mlp_forward(self.ctx, self.n_in, self.n_out, x.shape[0], self._p(params),
                                            self._p(x), self._p(y), *self._w()))
+        return y
+
+    def forward_noalloc(self, params, x, y):
+        """y[:n] = network(x) through csi_mlp_forward_noalloc: the library's own
+        per-GPU scratch instead of this object's work tensor; y is the caller's
+        float32 cuda tensor [n][n_out]."""
+        self._check(self.L.csi_mlp_forward_noalloc(self.ctx, self.n_in, self.n_out, x.shape[0], self._p(params),
+                                                   self._p(x), self._p(y)))
         return y
 
     def _batch(self, params, x, t, idx):

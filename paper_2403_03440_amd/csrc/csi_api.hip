@@ -2,6 +2,7 @@
 // tables, workspace layout inside the caller's device buffer, and the launch
 // sequence of each call.  No device memory is allocated here.
 #include <climits>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -42,8 +43,41 @@ IRunner *make_runner(int ns, int nt) {
 }
 }  // namespace csi
 
+// Device scratch of csi_mlp_forward_noalloc (packed BF16 operands of the
+// network), one copy per GPU, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel: its device address is taken once per
+// device with hipGetSymbolAddress (noalloc_scratch_ptr) and kept in the table.
+static __device__ __align__(256) unsigned char scratch[CSI_MLP_NOALLOC_SCRATCH_BYTES];
+
+struct NoallocTable {
+  std::mutex mu;
+  std::vector<void *> ptr;  // per device ordinal; nullptr until taken
+};
+NoallocTable &noalloc_table() {
+  static NoallocTable t;
+  return t;
+}
+
+// the device address of `scratch` on `device`, which must be current;
+// taken at the first call on that device
+hipError_t noalloc_scratch_ptr(int device, void **out) {
+  NoallocTable &t = noalloc_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if (t.ptr.size() <= size_t(device)) t.ptr.resize(size_t(device) + 1, nullptr);
+  if (!t.ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    t.ptr[device] = p;
+  }
+  *out = t.ptr[device];
+  return hipSuccess;
+}
+
 struct csi_ctx {
   int device = 0;
+  void *noalloc = nullptr;  // this device's address of `scratch`
   hipStream_t stream = nullptr;
   // surrogate inference beside the face kernels (created at the first
   // surrogate step; default priority)
@@ -246,6 +280,7 @@ int csi_create(csi_ctx **ctx, int device, void *hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) { delete c; return CSI_ERR_HIP; }
+  if (noalloc_scratch_ptr(device, &c->noalloc) != hipSuccess) { delete c; return CSI_ERR_HIP; }
   *ctx = c;
   return CSI_OK;
 }
@@ -1134,6 +1169,18 @@ int csi_mlp_forward(csi_ctx *c, int n_in, int n_out, int n, const float *params,
   char *w = static_cast<char *>(work);
   const MlpWork W = mlp_work(d, 1);
   return hip_check(c, mlp_forward_launch(d, params, x, n, y, w + W.off[0], c->stream), "mlp_forward launch");
+}
+
+int csi_mlp_forward_noalloc(csi_ctx *c, int n_in, int n_out, int n, const float *params, const float *x, float *y) {
+  if (!c) return CSI_ERR_ARG;
+  if (!mlp_ok(n_in, n_out) || n < 1 || !params || !x || !y)
+    return c->fail(CSI_ERR_ARG, "mlp_forward_noalloc: arguments");
+  const MlpDims d = mlp_dims(n_in, n_out);
+  if (size_t(d.nslots) * 16 > size_t(CSI_MLP_NOALLOC_SCRATCH_BYTES))
+    return c->fail(CSI_ERR_ARG, "mlp_forward_noalloc: the packed network needs " + std::to_string(size_t(d.nslots) * 16) +
+                                    " bytes of scratch, more than " + std::to_string(CSI_MLP_NOALLOC_SCRATCH_BYTES));
+  if (!c->noalloc) return c->fail(CSI_ERR_STATE, "mlp_forward_noalloc: no scratch address for this device");
+  return hip_check(c, mlp_forward_launch(d, params, x, n, y, c->noalloc, c->stream), "mlp_forward_noalloc launch");
 }
 
 int csi_mlp_grad(csi_ctx *c, const csi_mlp_batch *b, float *grad, double *loss) {
