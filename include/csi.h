@@ -176,14 +176,18 @@ int csi_step(csi_ctx *ctx, const csi_step_params *p, csi_step_stats *s);
 /* Which source Jacobian the split species block carries (Section 2.3, the
  * component operator solves Q_C with the flow variables unchanged; the paper
  * does not say which variables the chemical source is differentiated at).
- * reading 0 (default): J_C = d omega_s / d rho_r at fixed T, Tv.  reading 1:
+ * reading 0 (the default in two temperatures): J_C = d omega_s / d rho_r at
+ * fixed T, Tv.  reading 1 (the default in one temperature):
  * at fixed velocities and fixed internal (and vibrational) energy densities,
  * so that the temperatures follow the composition (the Jacobian of an
  * adiabatic constant-volume reactor): J_C + d omega_s/dT dT/d rho_r
- * (+ the Tv term).  Reading 1 applies to the exact block only (the
- * surrogate's block stays at fixed T, Tv) and needs ns >= 5
- * (CSI_ERR_UNSUPPORTED otherwise).  Errors: CSI_ERR_ARG for another value,
- * CSI_ERR_STATE before set_mechanism.  Reset by set_mechanism. */
+ * (+ the Tv term).  reading 2: as 1, with Tv held as well in two
+ * temperatures (rho e_ve takes the added mass's e_ve,r(Tv) out of the same
+ * internal energy, so T alone follows; the same as 1 in one temperature).  The reading also sets the targets of
+ * csi_sample_jacobians, so that a network trained on them learns the same
+ * block (its inputs T, Tv, rho, Y determine either reading).  Errors:
+ * CSI_ERR_ARG for another value, CSI_ERR_STATE before set_mechanism.
+ * set_mechanism restores the default of its temperature model. */
 int csi_set_species_jacobian(csi_ctx *ctx, int reading);
 
 /* Wall heat flux, the quantity whose convergence the paper tracks beside the
@@ -211,6 +215,17 @@ int csi_prim_to_cons(csi_ctx *ctx, int n, const double *rho_s, const double *u, 
  * Errors: CSI_ERR_ARG for any other value.  Changing the schedule invalidates
  * the records of the last implicit operator (csi_get_array). */
 int csi_set_sweep(csi_ctx *ctx, int schedule);
+/* Off-diagonal operator of the sweeps (Section 2.2: the neighbour terms are
+ * applied without storing their Jacobians).  op 0 (default): the linear
+ * Jacobian-vector product A_N(n) x of the spectral splitting.  op 1: the flux
+ * difference F(Q_N + x).n - F(Q_N).n in its place (coupled and flow parts;
+ * the species part is the same either way), which needs the neighbour's
+ * temperatures at Q_N + x inside the sweep: it runs in the per-hyperplane
+ * schedule (op 1 sets schedule 0) with FP64 sweeps only (CSI_ERR_UNSUPPORTED
+ * for CSI_MIXED).  A neighbour state Q_N + x that is not physical makes
+ * csi_implicit_op / csi_step return CSI_ERR_NONFINITE.  Errors: CSI_ERR_ARG
+ * for another value. */
+int csi_set_offdiag(csi_ctx *ctx, int op);
 /* Phase timing of csi_step with HIP events on the context's stream (on = 1 to
  * enable; on = 2 also records a per-strip trace of the group-schedule sweeps,
  * read with csi_get_array(ctx, "sweep_trace"); 0 disables both).
@@ -309,7 +324,9 @@ int csi_mlp_train_step(csi_ctx *ctx, const csi_mlp_batch *b, float *m, float *v,
 
 /* Training samples from the bound state: for cells 0..n-1 (n = min(N,
  * max_samples), returned in *n_written) the raw features x_raw [n][ns + 3] and
- * the exact J_C [n][ns * ns] (FP32).  There is no seed argument: the call is
+ * the exact J_C [n][ns * ns] (FP32) of the species block's reading
+ * (csi_set_species_jacobian).  Overwrites the diagonal-block hand-off of the
+ * last implicit operator (ns >= 5).  There is no seed argument: the call is
  * deterministic and takes every cell of the state (the training set is whole
  * snapshots of the solver's own iterates); the seeded draw happens in the
  * training, whose batch order comes from a seeded permutation of the rows. */

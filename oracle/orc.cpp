@@ -62,6 +62,10 @@ struct orc_ctx {
   // split species block: 0 = d omega / d rho_r at fixed T, Tv; 1 = at fixed
   // momenta and energies (Q_F unchanged), the temperatures following
   int jc_fixed_qf = 0;
+  // off-diagonal operator: 0 = linear Jacobian-vector product, 1 = flux
+  // difference F(Q_N + x) - F(Q_N) (coupled and flow parts)
+  int flux_diff = 0;
+  int fd_bad = -1;  // a cell whose neighbour state plus increment was not physical
   // dual time stepping: physical time step dt and theta (dt = 0: steady),
   // the time levels Q^n and Q^{n-1}
   double pt_dt = 0.0, pt_theta = 0.0;
@@ -354,6 +358,42 @@ void jvp_flow(const Mech &m, const CellD &C, double nx, double ny, const double 
   if (m.two_temp) out[4] = F[ns + 3].imag() / h;
 }
 
+// flux differences F(Q_N + x).n - F(Q_N).n in the same variables as the
+// Jacobian-vector products (the matrix-free alternative of A_N x; false if
+// Q_N + x is not a physical state)
+bool fdiff_coupled(const Mech &m, const CellD &C, double nx, double ny, const double *x, double *out) {
+  const int nb = m.nb();
+  double z[MAXV], z1[MAXV], q1[MAXV], F0[MAXV], F1[MAXV], Fz0[MAXV], Fz1[MAXV];
+  q_to_z<double>(m, C.q, z);
+  for (int k = 0; k < nb; ++k) z1[k] = z[k] + x[k];
+  z_to_q<double>(m, z1, q1);
+  Prim<double> P1;
+  if (!recover<double>(m, q1, P1)) return false;
+  phys_flux<double>(m, C.q, C.P, nx, ny, F0);
+  phys_flux<double>(m, q1, P1, nx, ny, F1);
+  vec_q_to_z<double>(m, F0, Fz0);
+  vec_q_to_z<double>(m, F1, Fz1);
+  for (int k = 0; k < nb; ++k) out[k] = Fz1[k] - Fz0[k];
+  return true;
+}
+
+bool fdiff_flow(const Mech &m, const CellD &C, double nx, double ny, const double *x, double *out) {
+  const int nf = m.nf(), ns = m.ns;
+  double q1[MAXV], F0[MAXV], F1[MAXV];
+  const double rho1 = C.P.rho + x[0];
+  for (int s = 0; s < ns; ++s) q1[s] = C.P.Y[s] * rho1;
+  for (int k = 1; k < nf; ++k) q1[ns + k - 1] = C.q[ns + k - 1] + x[k];
+  Prim<double> P1;
+  if (!recover<double>(m, q1, P1)) return false;
+  phys_flux<double>(m, C.q, C.P, nx, ny, F0);
+  phys_flux<double>(m, q1, P1, nx, ny, F1);
+  double m0 = 0.0, m1 = 0.0;
+  for (int s = 0; s < ns; ++s) { m0 += F0[s]; m1 += F1[s]; }
+  out[0] = m1 - m0;
+  for (int k = 1; k < nf; ++k) out[k] = F1[ns + k - 1] - F0[ns + k - 1];
+  return true;
+}
+
 }  // namespace
 
 // ================================================================== API
@@ -376,6 +416,10 @@ int orc_set_option(orc_ctx *c, const char *name, double value) {
   const std::string n(name);
   if (n == "jc_fixed_qf") {
     c->jc_fixed_qf = int(value);
+    return 0;
+  }
+  if (n == "flux_diff") {
+    c->flux_diff = value != 0.0;
     return 0;
   }
   return c->fail(-1, "unknown option " + n);
@@ -440,6 +484,9 @@ int orc_set_mechanism(orc_ctx *c, const orc_mechanism *mm) {
   }
   m.mu_ref = mm->mu_ref; m.T_ref = mm->T_ref; m.mu_exp = mm->mu_exp;
   c->has_mech = true;
+  // default species-block reading: the temperature following the composition
+  // at fixed velocities and internal energy in one temperature, fixed T, Tv in two
+  c->jc_fixed_qf = mm->two_temp ? 0 : 2;
   c->has_state = false;
   c->has_fs = false;
   c->has_res = false;
@@ -743,12 +790,18 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
         cplx qc[MAXV], sc[MAXV];
         for (int k = 0; k < nv; ++k) qc[k] = P.q[k];
         qc[col] += cplx(0.0, h);
-        if (c->jc_fixed_qf == 2) {
+        if (c->jc_fixed_qf >= 2) {
           // velocities and the internal energy density held: the added mass
           // carries its momentum and kinetic energy
           qc[ns] += cplx(0.0, h * P.P.u);
           qc[ns + 1] += cplx(0.0, h * P.P.v);
           qc[ns + 2] += cplx(0.0, h * 0.5 * (P.P.u * P.P.u + P.P.v * P.P.v));
+        }
+        if (c->jc_fixed_qf == 3 && m.two_temp) {
+          // and the vibrational temperature held: the vibrational-electronic
+          // energy density takes the added mass's e_ve,r(Tv) out of the same
+          // internal energy
+          qc[ns + 3] += cplx(0.0, h * e_ve<double>(m, col, P.P.Tv));
         }
         source<cplx>(m, qc, sc);
         for (int r = 0; r < ns; ++r) c->JC[(size_t(r) * ns + col) * N + p] = sc[r].imag() / h;
@@ -843,24 +896,35 @@ enum Part { P_COUPLED, P_FLOW, P_SPECIES };
 // with (nx, ny) the outward unit normal of P (paper Section 2.2: spectral
 // splitting A+- = (A +- lambda I)/2 and the viscous spectral approximation;
 // Section 2.3: flow radius |U|+c, species radius |U| and the scalar species operator)
-void apply_off(const Mech &m, Part part, const Face &F, double nx, double ny, const CellD &Cn,
-               const double *x, double *out) {
+bool apply_off(const Mech &m, Part part, const Face &F, double nx, double ny, const CellD &Cn,
+               const double *x, double *out, bool fdiff) {
   if (part == P_COUPLED) {
     int n = m.nb();
     double a[MAXV];
-    jvp_coupled(m, Cn, nx, ny, x, a);
+    if (fdiff) {
+      if (!fdiff_coupled(m, Cn, nx, ny, x, a)) return false;
+    } else {
+      jvp_coupled(m, Cn, nx, ny, x, a);
+    }
     for (int k = 0; k < n; ++k) out[k] = 0.5 * F.S * (a[k] - F.lam * x[k]) - F.lvK * F.S * x[k];
   } else if (part == P_FLOW) {
     int n = m.nf();
     double a[MAXV];
-    jvp_flow(m, Cn, nx, ny, x, a);
+    if (fdiff) {
+      if (!fdiff_flow(m, Cn, nx, ny, x, a)) return false;
+    } else {
+      jvp_flow(m, Cn, nx, ny, x, a);
+    }
     for (int k = 0; k < n; ++k) out[k] = 0.5 * F.S * (a[k] - F.lam * x[k]) - F.lvF * F.S * x[k];
   } else {
+    // species part: the flux difference at unchanged flow variables is
+    // exactly (u.n) x, the same as the linear operator
     int n = m.ns;
     double un = Cn.P.u * nx + Cn.P.v * ny;
     double coef = 0.5 * F.S * (un - F.Uabs) - F.lvC * F.S;
     for (int k = 0; k < n; ++k) out[k] = coef * x[k];
   }
+  return true;
 }
 
 struct PartInfo {
@@ -886,6 +950,11 @@ void solve_block(orc_ctx *c, const PartInfo &pi, int p, double *x) {
   lu_solve(n, A, piv, x);
 }
 
+void note_fd_bad(orc_ctx *c, int p) {
+#pragma omp critical
+  c->fd_bad = (c->fd_bad < 0 || p < c->fd_bad) ? p : c->fd_bad;
+}
+
 // forward: (D+L) dQ* = b ; backward: (D+U) dQ = D dQ*  (paper Section 2.2)
 void sweep_cell_fwd(orc_ctx *c, Part part, const PartInfo &pi, int i, int j, const std::vector<double> &b,
                     std::vector<double> &xs) {
@@ -898,14 +967,14 @@ void sweep_cell_fwd(orc_ctx *c, Part part, const PartInfo &pi, int i, int j, con
     const Face &F = c->fI[c->fii(i, j)];
     int q = c->ci(i - 1, j);
     for (int k = 0; k < n; ++k) x[k] = xs[size_t(off + k) * N + q];
-    apply_off(m, part, F, -F.nx, -F.ny, c->cells[c->pc(i - 1, j)], x, o);
+    if (!apply_off(m, part, F, -F.nx, -F.ny, c->cells[c->pc(i - 1, j)], x, o, c->flux_diff != 0)) note_fd_bad(c, p);
     for (int k = 0; k < n; ++k) r[k] -= o[k];
   }
   if (j > 0) {  // south neighbour
     const Face &F = c->fJ[c->fji(i, j)];
     int q = c->ci(i, j - 1);
     for (int k = 0; k < n; ++k) x[k] = xs[size_t(off + k) * N + q];
-    apply_off(m, part, F, -F.nx, -F.ny, c->cells[c->pc(i, j - 1)], x, o);
+    if (!apply_off(m, part, F, -F.nx, -F.ny, c->cells[c->pc(i, j - 1)], x, o, c->flux_diff != 0)) note_fd_bad(c, p);
     for (int k = 0; k < n; ++k) r[k] -= o[k];
   }
   solve_block(c, pi, p, r);
@@ -923,14 +992,14 @@ void sweep_cell_bwd(orc_ctx *c, Part part, const PartInfo &pi, int i, int j, con
     const Face &F = c->fI[c->fii(i + 1, j)];
     int q = c->ci(i + 1, j);
     for (int k = 0; k < n; ++k) x[k] = x_out[size_t(off + k) * N + q];
-    apply_off(m, part, F, F.nx, F.ny, c->cells[c->pc(i + 1, j)], x, o);
+    if (!apply_off(m, part, F, F.nx, F.ny, c->cells[c->pc(i + 1, j)], x, o, c->flux_diff != 0)) note_fd_bad(c, p);
     for (int k = 0; k < n; ++k) r[k] += o[k];
   }
   if (j < c->nj - 1) {  // north neighbour
     const Face &F = c->fJ[c->fji(i, j + 1)];
     int q = c->ci(i, j + 1);
     for (int k = 0; k < n; ++k) x[k] = x_out[size_t(off + k) * N + q];
-    apply_off(m, part, F, F.nx, F.ny, c->cells[c->pc(i, j + 1)], x, o);
+    if (!apply_off(m, part, F, F.nx, F.ny, c->cells[c->pc(i, j + 1)], x, o, c->flux_diff != 0)) note_fd_bad(c, p);
     for (int k = 0; k < n; ++k) r[k] += o[k];
   }
   solve_block(c, pi, p, r);
@@ -966,6 +1035,7 @@ int sweeps(orc_ctx *c, int mode, int order, const std::vector<double> &b) {
   const int N = c->N, ns_ = nsol_of(c->m, mode);
   c->dqs.assign(size_t(ns_) * N, 0.0);
   c->dq.assign(size_t(ns_) * N, 0.0);
+  c->fd_bad = -1;
   if (mode == ORC_COUPLED) {
     run_sweeps(c, P_COUPLED, mode, order, b, c->dqs, c->dq);
   } else {
@@ -974,6 +1044,8 @@ int sweeps(orc_ctx *c, int mode, int order, const std::vector<double> &b) {
     run_sweeps(c, P_SPECIES, mode, order, b, c->dqs, c->dq);
   }
   c->last_mode = mode;
+  if (c->fd_bad >= 0)
+    return c->fail(-4, "flux difference at a non-physical neighbour state (cell " + std::to_string(c->fd_bad) + ")");
   return 0;
 }
 
@@ -1182,7 +1254,7 @@ int orc_dense_operator(orc_ctx *c, int mode, double *D, double *L, double *U) {
           for (int col = 0; col < n; ++col) {
             double e[MAXV] = {0}, o[MAXV];
             e[col] = 1.0;
-            apply_off(m, part, *nb.F, nb.sgn * nb.F->nx, nb.sgn * nb.F->ny, c->cells[c->pc(nb.in, nb.jn)], e, o);
+            (void)apply_off(m, part, *nb.F, nb.sgn * nb.F->nx, nb.sgn * nb.F->ny, c->cells[c->pc(nb.in, nb.jn)], e, o, false);
             for (int r = 0; r < n; ++r)
               nb.M[(size_t(p) * nsol + off + r) * dim + size_t(q) * nsol + off + col] = o[r];
           }
@@ -1261,6 +1333,23 @@ int orc_point_flux_jacobian(orc_ctx *c, const double *q, double nx, double ny, d
     if (!recover<cplx>(m, qc, P)) return -4;
     phys_flux<cplx>(m, qc, P, nx, ny, F);
     for (int r = 0; r < nv; ++r) A[r * nv + col] = F[r].imag() / h;
+  }
+  return 0;
+}
+
+int orc_point_offdiag(orc_ctx *c, const double *q, double nx, double ny, int mode, int fd, const double *x,
+                      double *out) {
+  if (!c || !c->has_mech || !q || !x || !out) return -1;
+  const Mech &m = c->m;
+  CellD C;
+  for (int k = 0; k < m.nv(); ++k) C.q[k] = q[k];
+  if (!recover<double>(m, C.q, C.P)) return c->fail(-4, "non-physical state");
+  if (mode == ORC_COUPLED) {
+    if (fd) return fdiff_coupled(m, C, nx, ny, x, out) ? 0 : c->fail(-4, "non-physical perturbed state");
+    jvp_coupled(m, C, nx, ny, x, out);
+  } else {
+    if (fd) return fdiff_flow(m, C, nx, ny, x, out) ? 0 : c->fail(-4, "non-physical perturbed state");
+    jvp_flow(m, C, nx, ny, x, out);
   }
   return 0;
 }

@@ -54,7 +54,12 @@ void orc_destroy(orc_ctx *ctx);
 const char *orc_last_error(const orc_ctx *ctx);
 int orc_set_threads(orc_ctx *ctx, int n);
 /* named options: "jc_fixed_qf" (0: split species block at fixed T, Tv;
- * 1: at fixed momenta and energies, the temperatures following) */
+ * 1: at fixed momenta and energies; 2: at fixed velocities and internal
+ * energy densities, the temperatures following; 3: as 2 with Tv held; the
+ * default after orc_set_mechanism is 2 in one temperature and 0 in two);
+ * "flux_diff" (0: linear
+ * Jacobian-vector products off the diagonal; 1: flux differences
+ * F(Q_N + x) - F(Q_N)) */
 int orc_set_option(orc_ctx *ctx, const char *name, double value);
 /* dual time stepping (paper Section 2.2, Eq. (linearizedimplicit)): physical
  * step dt (0: steady) and theta; orc_advance_time: Q^{n-1} <- Q^n <- Q
@@ -108,6 +113,10 @@ int orc_point_flux_jacobian(orc_ctx *ctx, const double *q, double nx, double ny,
 int orc_point_flux(orc_ctx *ctx, const double *q, double nx, double ny, double *F);
 /* HLLE face flux between left state qL and right state qR, unit normal (nx, ny) from L to R */
 int orc_point_hlle(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double *F);
+/* off-diagonal neighbour term at state q: mode 0 coupled (x in z), 1 flow part
+ * (x in Q_F at frozen Y); fd 0: A(n) x, fd 1: F(q + x).n - F(q).n */
+int orc_point_offdiag(orc_ctx *ctx, const double *q, double nx, double ny, int mode, int fd, const double *x,
+                      double *out);
 int orc_point_source_jacobian(orc_ctx *ctx, const double *q, int which, double *J);
 
 #ifdef __cplusplus

@@ -25,7 +25,7 @@ _ip = C.POINTER(C.c_int)
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so with g++ (plain FP64, no fused multiply-add contraction)."""
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+    cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
            "-o", LIB_PATH + ".tmp"] + srcs
     if verbose:
         print(" ".join(cmd))
@@ -258,6 +258,15 @@ class Oracle:
         self._check(self.L.orc_point_flux_jacobian(self.ctx, p, C.c_double(nx), C.c_double(ny),
                                                    A.ctypes.data_as(_dp)))
         return A
+
+    def point_offdiag(self, q, nx, ny, mode, fd, x):
+        n = self.mech.nb if mode == COUPLED else self.mech.nf
+        out = np.zeros(n)
+        a, p = _d(q)
+        b, px = _d(x)
+        self._check(self.L.orc_point_offdiag(self.ctx, p, C.c_double(nx), C.c_double(ny), mode, int(fd), px,
+                                             out.ctypes.data_as(_dp)))
+        return out
 
     def point_source_jacobian(self, q, which):
         m = self.mech

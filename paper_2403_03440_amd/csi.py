@@ -33,7 +33,7 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
             "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate", "csi_mlp_forward_noalloc",
             "csi_set_species_jacobian", "csi_set_physical_time", "csi_advance_time",
-            "csi_set_time_levels"]
+            "csi_set_time_levels", "csi_set_offdiag"]
 PHASES = ["prim", "faces", "cell", "block", "norms", "sweep_fwd", "sweep_bwd", "update"]
 
 
@@ -264,6 +264,11 @@ class Solver:
     def set_sweep(self, schedule):
         """0: one launch per i+j hyperplane; 1: persistent group kernels (default)"""
         self._check(self.L.csi_set_sweep(self.ctx, int(schedule)))
+
+    def set_offdiag(self, op):
+        """0: linear Jacobian-vector products; 1: flux differences (FP64,
+        per-hyperplane schedule)"""
+        self._check(self.L.csi_set_offdiag(self.ctx, int(op)))
 
     def set_timing(self, on=True):
         """1: phase timing with HIP events; 2: also a per-strip sweep trace (get("sweep_trace"))"""

@@ -116,12 +116,15 @@ struct csi_ctx {
   double phase_ms[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   // split species block: 0 = J_C at fixed T, Tv; 1 = at fixed velocities,
-  // internal and vibrational energy densities (cell kernel flag bit 3)
+  // internal and vibrational energy densities (cell kernel flag bit 3); 2 = at
+  // fixed velocities, internal energy density and Tv (flag bits 3 and 4)
   int jc_reading = 0;
   // physical time (dual time stepping): the unsteady terms carry
   // pt_a = (1 + theta) / dt and pt_b = theta / dt (both 0: steady)
   double pt_a = 0.0, pt_b = 0.0;
-  int jc_flag() const { return jc_reading ? 8 : 0; }
+  // off-diagonal operator: 0 linear Jacobian-vector products, 1 flux differences
+  int fdiff = 0;
+  int jc_flag() const { return jc_reading == 0 ? 0 : (jc_reading == 1 ? 8 : 8 | 16); }
 
   int nv() const { return ns + 3 + (nt == 2 ? 1 : 0); }
   int nf() const { return nt == 2 ? 5 : 4; }
@@ -327,7 +330,9 @@ int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
   c->nt = mm->two_temp ? 2 : 1;
   c->group_c = 1;  // persistent group kernels
   c->has_mech = true;
-  c->jc_reading = 0;
+  // the species block with the temperature following the composition in one
+  // temperature; at fixed T, Tv in two (the default readings)
+  c->jc_reading = mm->two_temp ? 0 : 1;
   c->has_fs = false;
   c->bound = false;
   c->has_state = false;
@@ -396,6 +401,7 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.qnm1 = D(50);
   w.pt_a = c->pt_a;
   w.pt_b = c->pt_b;
+  w.fdiff = c->fdiff;
   w.trace = c->trace > 0 ? c->trace_buf : nullptr;
   c->has_sur = false;
   w.group_c = c->group_c;
@@ -539,6 +545,8 @@ int csi_implicit_op(csi_ctx *c, int mode, int precision, int jac) {
   if (jac == CSI_JAC_SURROGATE && mode != CSI_SPLIT) return c->fail(CSI_ERR_ARG, "the surrogate serves the split form");
   if (jac == CSI_JAC_SURROGATE && !c->has_sur) return c->fail(CSI_ERR_STATE, "no surrogate installed");
   if (!ready(c) || !c->has_res) return c->fail(CSI_ERR_STATE, "implicit_op before residual");
+  if (c->fdiff && precision != CSI_FP64)
+    return c->fail(CSI_ERR_UNSUPPORTED, "flux-difference off-diagonal operator: FP64 sweeps only");
   hipError_t e = hipSuccess;
   if (jac == CSI_JAC_SURROGATE) e = c->run->surrogate(c->g, c->w, c->stream, false);
   if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, 0.0, mode, precision, (jac == CSI_JAC_SURROGATE ? 6 : 2) | c->jc_flag(), false);
@@ -550,6 +558,9 @@ int csi_implicit_op(csi_ctx *c, int mode, int precision, int jac) {
   if (fl[FL_ABORT]) return c->fail(CSI_ERR_HIP, "implicit_op: a sweep wave timed out waiting for its neighbour");
   if (fl[FL_SING] != INT_MAX)
     return c->fail(CSI_ERR_SINGULAR, "singular diagonal block at cell " + std::to_string(fl[FL_SING]));
+  if (fl[FL_BAD] != INT_MAX)
+    return c->fail(CSI_ERR_NONFINITE, "flux difference at a non-physical neighbour state (cell " +
+                                          std::to_string(fl[FL_BAD]) + ")");
   c->last_mode = mode;
   c->last_prec = precision;
   c->has_dq = true;
@@ -589,6 +600,8 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   const bool sur = p->jac == CSI_JAC_SURROGATE;
   if (sur && p->mode != CSI_SPLIT) return c->fail(CSI_ERR_ARG, "step: the surrogate serves the split form");
   if (sur && !c->has_sur) return c->fail(CSI_ERR_STATE, "step: no surrogate installed");
+  if (c->fdiff && p->precision != CSI_FP64)
+    return c->fail(CSI_ERR_UNSUPPORTED, "flux-difference off-diagonal operator: FP64 sweeps only");
   int rc = reset_flags(c);
   if (rc) return rc;
   if (sur && !c->side) {
@@ -735,10 +748,8 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
 
 int csi_set_species_jacobian(csi_ctx *c, int reading) {
   if (!c) return CSI_ERR_ARG;
-  if (reading != 0 && reading != 1) return c->fail(CSI_ERR_ARG, "set_species_jacobian: reading must be 0 or 1");
+  if (reading < 0 || reading > 2) return c->fail(CSI_ERR_ARG, "set_species_jacobian: reading must be 0, 1 or 2");
   if (!c->has_mech) return c->fail(CSI_ERR_STATE, "set_species_jacobian before set_mechanism");
-  if (reading == 1 && c->ns < BLOCK_NS_MIN)
-    return c->fail(CSI_ERR_UNSUPPORTED, "set_species_jacobian: reading 1 needs ns >= " + std::to_string(BLOCK_NS_MIN));
   c->jc_reading = reading;
   c->has_dq = false;
   return CSI_OK;
@@ -779,6 +790,16 @@ int csi_set_sweep(csi_ctx *c, int schedule) {
   c->w.group_c = schedule;
   c->last_mode = -1;  // the records of the last operator are in the old layout
   c->has_res = false;
+  c->has_dq = false;
+  return CSI_OK;
+}
+
+int csi_set_offdiag(csi_ctx *c, int op) {
+  if (!c) return CSI_ERR_ARG;
+  if (op != 0 && op != 1) return c->fail(CSI_ERR_ARG, "off-diagonal operator must be 0 or 1");
+  c->fdiff = op;
+  c->w.fdiff = op;
+  if (op == 1) return csi_set_sweep(c, 0);  // flux differences run in the per-hyperplane sweeps
   c->has_dq = false;
   return CSI_OK;
 }
@@ -1203,7 +1224,7 @@ int csi_sample_jacobians(csi_ctx *c, int max_samples, float *x_raw, float *jc, i
   if (max_samples < 1 || !x_raw || !jc) return c->fail(CSI_ERR_ARG, "sample_jacobians: arguments");
   if (!ready(c)) return c->fail(CSI_ERR_STATE, "sample_jacobians: workspace/state not set");
   const int n = max_samples < c->N ? max_samples : c->N;
-  int rc = hip_check(c, c->run->sample(c->g, c->w, c->stream, n, x_raw, jc), "sample launch");
+  int rc = hip_check(c, c->run->sample(c->g, c->w, c->stream, n, x_raw, jc, c->jc_flag()), "sample launch");
   if (rc) return rc;
   int fl[FL_N];
   if ((rc = read_flags(c, fl))) return rc;

@@ -38,6 +38,8 @@ struct BlockOut {
   unsigned long long *ddfail;  // cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off
   int *bad;                    // first singular cell
+  float *jc_out;               // non-null: write the species block's J_C [n_lim][ns][ns] (FP32) and stop
+  long n_lim;                  // cells written with jc_out
 };
 
 template <int NS, int NT, int MODE> struct BlockDims {
@@ -48,7 +50,8 @@ template <int NS, int NT, int MODE> struct BlockDims {
   static constexpr bool SUMS = MODE == 0 || NT == 2;
   // per-group LDS (doubles): hand-off X | dT/dq | dTv/dq | Y, then g/RT | h/RT^2,
   // then a scratch area
-  static constexpr int O_X = 0, O_TQ = NS, O_Y = NS + 2 * NV, O_GH = 2 * NS + 2 * NV, O_S = 4 * NS + 2 * NV;
+  static constexpr int O_X = 0, O_TQ = NS, O_Y = NS + 2 * NV, O_GH = 2 * NS + 2 * NV, O_EV = 4 * NS + 2 * NV;
+  static constexpr int O_S = O_EV + (NT == 2 ? NS : 0);
   static constexpr int NHB = 2 * NS + 2 * NV;
   // the scratch area holds, one after the other (wave syncs between them):
   // the chunk's reaction records [G][RW], the scalar sums [NSUM][G] + NSUM,
@@ -62,6 +65,17 @@ template <int NS, int NT, int MODE> struct BlockDims {
   static constexpr int SCR = SCR0 > SCR1 ? SCR0 : SCR1;
   static constexpr int BUF = O_S + SCR;
 };
+
+// Workgroups are handed to the eight XCDs in turn (b mod 8), and each XCD has
+// its own L2.  Cells of adjacent blocks share cache lines of the per-cell
+// fields (three to five cells per block, sixteen doubles per line), so block b
+// takes the logical position that gives every XCD one contiguous run of
+// blocks: the lines a block fetches are then mostly in its own XCD's L2.
+// A bijection of [0, n).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n) {
+  const unsigned x = b % 8u, k = b / 8u, per = n / 8u, rem = n % 8u;
+  return x * per + (x < rem ? x : rem) + k;
+}
 
 // Exchange point between the lanes of one wave through LDS: stores made before
 // it are seen by loads after it.  The LDS operations of a wave complete in
@@ -280,8 +294,8 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
   const int grp = lane / G, k = lane - grp * G;
   const bool live = grp < C;  // lanes past the last group read group 0's buffer and write nothing
   double *buf = sh[live ? grp : 0];
-  const long cell = long(blockIdx.x) * C + grp;
-  const bool real = live && cell < g.N;
+  const long cell = long(xcd_block(blockIdx.x, gridDim.x)) * C + grp;
+  const bool real = live && cell < (out.jc_out ? out.n_lim : long(g.N));
   const int p = int(real ? cell : 0);
   const int i = p % g.ni, j = p / g.ni;
   const int pc = padc(g, i, j);
@@ -297,6 +311,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     if (k < NS) {
       GH[k] = gRT(m, k, T, lnT);
       GH[NS + k] = hRT2(m, k, T);
+      if (NT == 2) buf[BD::O_EV + k] = eve_s(m, k, Tv);
     }
   }
   wave_sync();
@@ -334,13 +349,32 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
       if (live && r0 + k < m.nr) reaction_record<NS, NT>(m, r0 + k, T, Tv, lnT, lnTv, lnc0, X, GH, scr + k * RW);
       wave_sync();
       const int nk = m.nr - r0 < G ? m.nr - r0 : G;
-      double av[G];  // M_t nu_tr of the chunk's reactions, loaded together
+      // the chunk's reactions that change this lane's species: bit kk of
+      // `mask`, their net coefficients packed three bits each, ten per word;
+      // each lane then visits only its own reactions, in ascending order
+      constexpr int NW = (G + 9) / 10;
+      unsigned long long mask = 0ull;
+      unsigned pk[NW];
 #pragma unroll
-      for (int kk = 0; kk < G; ++kk) av[kk] = t >= 0 && kk < nk ? m.nuM[r0 + kk][tc] : 0.0;
+      for (int w = 0; w < NW; ++w) pk[w] = 0u;
 #pragma unroll
       for (int kk = 0; kk < G; ++kk) {
-        const double a = av[kk];
-        if (kk < nk && a != 0.0) {
+        const int v = live && t >= 0 && kk < nk ? int(m.nu_net[r0 + kk][tc]) : 0;
+        if (v != 0) mask |= 1ull << kk;
+        pk[kk / 10] |= unsigned(v & 7) << (3 * (kk % 10));
+      }
+      const double Mt = m.M[tc];
+      while (__ballot(mask != 0ull) != 0ull) {
+        if (mask != 0ull) {
+          const int kk = __builtin_ctzll(mask);
+          mask &= mask - 1ull;
+          const int wsel = kk / 10;
+          unsigned wd = pk[0];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) wd = wsel == w ? pk[w] : wd;
+          int v = int((wd >> (3 * (kk - 10 * wsel))) & 7u);
+          v = v >= 4 ? v - 8 : v;
+          const double a = Mt * double(v);  // M_t nu_tr
           const double *D = scr + kk * RW;
 #pragma unroll
           for (int u = 0; u < NS; ++u) row[u] += a * D[u];
@@ -454,16 +488,32 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     // the composition: J_C += d omega_t/dT dT/d rho_c (+ the Tv term), the
     // temperature derivatives taken along the direction that adds mass at the
     // cell's velocity and kinetic energy
+    // (flags bit 4, two temperatures: Tv held too, rho e_ve taking the added
+    // mass's e_ve,r(Tv) out of the same internal energy)
     const bool te = (flags & 8) != 0 && !use_sur;
+    const bool hold_tv = NT == 2 && (flags & 16) != 0;
     const double uu = prim[F_U * NP + pc], vv = prim[F_V * NP + pc], ke = 0.5 * (uu * uu + vv * vv);
+    double jr[NS];
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
       double jc = use_sur ? double(out.Jsur[size_t(tc * NS + c) * g.N + p]) : row[c];
       if (te) {
-        jc += dwT * (TQ[c] + uu * TQ[NS] + vv * TQ[NS + 1] + ke * TQ[NS + 2]);
-        if (NT == 2) jc += dwTv * (TQ[NV + c] + uu * TQ[NV + NS] + vv * TQ[NV + NS + 1] + ke * TQ[NV + NS + 2]);
+        const double ev = hold_tv ? buf[BD::O_EV + c] : 0.0;
+        jc += dwT * (TQ[c] + uu * TQ[NS] + vv * TQ[NS + 1] + ke * TQ[NS + 2] + (NT == 2 ? ev * TQ[NS + 3] : 0.0));
+        if (NT == 2)
+          jc += dwTv * (TQ[NV + c] + uu * TQ[NV + NS] + vv * TQ[NV + NS + 1] + ke * TQ[NV + NS + 2] +
+                        ev * TQ[NV + NS + 3]);
       }
+      jr[c] = jc;
       A[c] = (c == k ? dC : 0.0) - Vp * jc;
+    }
+    // training samples of the species block's source Jacobian (row-major
+    // (s, r) per cell); the whole wave leaves here
+    if (out.jc_out) {
+      if (real && t >= 0)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) out.jc_out[(size_t(p) * NS + t) * NS + c] = float(jr[c]);
+      return;
     }
     // flow block: diagonal 1/dF, and in two temperatures the rho e_ve row
     // -V d omega_ve / d Q_F (frozen Y) eliminated in closed form

@@ -474,6 +474,47 @@ __host__ __device__ inline long group_blk(const GroupMap &m, int i, int j, int &
 // the split-radius diagonals of Section 2.3) and their inverses, and the RHS.
 // mode 0: coupled (nb x nb block in z = rho, momenta, energies, rho_1..rho_{ns-1})
 // mode 1: split (flow block in closed form, ns x ns species block)
+// Per-cell hand-off from the cell kernel to k_block (fields from HB_X on,
+// [field][N]): X_s = rho_s / M_s, dT/dq_c, dTv/dq_c for every stored variable,
+// Y_s.
+template <int NS, int NT>
+__device__ __forceinline__ void write_handoff(const Mech &m, const double *rs, const Prim<NS, NT> &P, double *diag,
+                                              long N, int p) {
+  constexpr int NV = Dims<NS, NT>::nv;
+  double *hb = diag + size_t(HB_X) * N + p;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    hb[size_t(s) * N] = rs[s] / m.M[s];
+    hb[size_t(NS + 2 * NV + s) * N] = P.Y[s];
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double dT, dTv;
+    temp_derivs<NS, NT>(P, c, dT, dTv);
+    hb[size_t(NS + c) * N] = dT;
+    hb[size_t(NS + NV + c) * N] = dTv;
+  }
+}
+
+// The hand-off alone, for cells 0..n-1 of the state (training samples of the
+// block kernel's species Jacobian)
+template <int NS, int NT>
+__global__ void __launch_bounds__(256) k_handoff(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
+                                                 const double *__restrict__ prim, int n, double *__restrict__ diag) {
+  constexpr int NV = Dims<NS, NT>::nv;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Mech &m = *mech;
+  const size_t NP = g.NP;
+  const int pc = padc(g, p % g.ni, p / g.ni);
+  double q[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) q[k] = Q[size_t(k) * g.N + p];
+  Prim<NS, NT> P;
+  prim_from_q<NS, NT>(m, q, P, prim[F_T * NP + pc], prim[F_TV * NP + pc]);
+  write_handoff<NS, NT>(m, q, P, diag, g.N, p);
+}
+
 struct CellOut {
   double *R, *dtau, *part;     // part: per-block norm partials [2][nblocks]
   void *Dinv;                  // coupled: nb*nb fields; split: DF 6 fields then DC ns*ns fields
@@ -578,21 +619,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     // temperature derivatives w.r.t. stored variables (recomputed from the state)
     Prim<NS, NT> P;
     prim_from_q<NS, NT>(m, q, P, T, Tv);  // T, Tv: k_prim's solution for this q
-    if constexpr (BLK) {
-      double *hb = out.diag + size_t(HB_X) * g.N + p;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        hb[size_t(s) * g.N] = rs[s] / m.M[s];
-        hb[size_t(NS + 2 * NV + s) * g.N] = P.Y[s];
-      }
-#pragma unroll
-      for (int c = 0; c < NV; ++c) {
-        double dT, dTv;
-        temp_derivs<NS, NT>(P, c, dT, dTv);
-        hb[size_t(NS + c) * g.N] = dT;
-        hb[size_t(NS + NV + c) * g.N] = dTv;
-      }
-    }
+    if constexpr (BLK) write_handoff<NS, NT>(m, rs, P, out.diag, g.N, p);
     // pseudo-time and physical-time diagonal: V / dtau + (1 + theta) V / dt
     double Vdt = Vp / dt + Vp * out.pt_a;
     // hyperplane schedule: cell-major records (field f at f N + p)
@@ -757,10 +784,20 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         }
       }
       if (!use_sur) {
+        // flags bit 3: temperatures following the composition at fixed
+        // velocities and internal energy densities
+        double dTc[NS], dTvc[NS];
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+          dTc[c] = 0.0;
+          dTvc[c] = 0.0;
+          if (flags & 8) temp_derivs_fixed_e<NS, NT>(m, P, c, (flags & 16) != 0, dTc[c], dTvc[c]);
+        }
 #pragma unroll
         for (int r = 0; r < NS; ++r)
 #pragma unroll
-          for (int c = 0; c < NS; ++c) A[r][c] = (r == c ? dC : 0.0) - Vp * C.dw_dr[r][c];
+          for (int c = 0; c < NS; ++c)
+            A[r][c] = (r == c ? dC : 0.0) - Vp * (C.dw_dr[r][c] + C.dw_dT[r] * dTc[c] + C.dw_dTv[r] * dTvc[c]);
         ok = invert<NS>(A, Ai);
       }
       }

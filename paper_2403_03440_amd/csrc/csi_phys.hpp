@@ -46,6 +46,7 @@ struct Mech {
   double mu_ref, T_ref, mu_exp;
   double iM[MAXS];          // 1 / M_s
   double nuM[MAXR][MAXS];   // M_s (nu''_rs - nu'_rs): weight of reaction r's rate in omega_s
+  signed char nu_net[MAXR][MAXS];  // nu''_rs - nu'_rs (at most 3 in magnitude)
 };
 
 template <int NS, int NT> struct Dims {
@@ -537,6 +538,35 @@ CSI_HD void temp_derivs(const Prim<NS, NT> &P, int c, double &dT, double &dTv) {
   else if (c == NS + 1) { dT = -P.v * P.dT_dE; dTv = P.tvT ? dT : 0.0; }
   else if (c == NS + 2) { dT = P.dT_dE; dTv = P.tvT ? dT : 0.0; }
   else { dT = P.dT_dv; dTv = P.dTv_dv; }
+}
+
+// Temperature derivatives along the direction that adds mass of species r at
+// the cell's velocity and internal energy density (rho u, rho v and rho E
+// change by u, v and |u|^2 / 2 per unit mass; rho e_ve is held): the split
+// species block with the temperatures following the composition.
+// hold_tv (two temperatures): the vibrational temperature held as well, rho
+// e_ve taking the added mass's e_ve,r(Tv) out of the same internal energy.
+template <int NS, int NT>
+CSI_HD void temp_derivs_fixed_e(const Mech &m, const Prim<NS, NT> &P, int r, bool hold_tv, double &dT,
+                                double &dTv) {
+  double a, b;
+  const double ke = 0.5 * (P.u * P.u + P.v * P.v);
+  temp_derivs<NS, NT>(P, r, dT, dTv);
+  if (NT == 2 && hold_tv) {
+    const double ev = eve_s(m, r, P.Tv);
+    temp_derivs<NS, NT>(P, NS + 3, a, b);
+    dT += ev * a;
+    dTv += ev * b;
+  }
+  temp_derivs<NS, NT>(P, NS, a, b);
+  dT += P.u * a;
+  dTv += P.u * b;
+  temp_derivs<NS, NT>(P, NS + 1, a, b);
+  dT += P.v * a;
+  dTv += P.v * b;
+  temp_derivs<NS, NT>(P, NS + 2, a, b);
+  dT += ke * a;
+  dTv += ke * b;
 }
 
 // Coupled source Jacobian dS_z/dz in the coupled unknowns

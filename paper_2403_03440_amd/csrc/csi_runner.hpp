@@ -20,6 +20,7 @@ struct WS {
   double *qbak;               // [nv][N] state at the start of csi_step (surrogate divergence fallback)
   double *qn, *qnm1;          // [nv][N] physical-time levels Q^n, Q^{n-1} (dual time stepping)
   double pt_a, pt_b;          // (1 + theta) / dt and theta / dt (0: steady)
+  int fdiff;                  // off-diagonal flux differences (hyperplane schedule, FP64) instead of the JVP
   int *flags;  // [0] bad cell (INT_MAX = none), [1] done, [2] it_done, [3] clipped cells, [4] singular cell
   int nblk_cell, hist_max;
   int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels
@@ -49,7 +50,8 @@ class IRunner {
   virtual hipError_t norms(const WS &w, hipStream_t st, int it, double tol, bool stoppable,
                            StallArgs stall = StallArgs{nullptr, 0, 0, 0.0}) = 0;
   virtual hipError_t surrogate(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
-  virtual hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc) = 0;
+  // flags bit 3: the species block's reading with the temperatures following the composition
+  virtual hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc, int flags) = 0;
   virtual hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable,
                             hipEvent_t mid = nullptr) = 0;
   virtual hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind,
@@ -113,7 +115,7 @@ template <int NS, int NT> class Runner : public IRunner {
     if constexpr (NS >= BLOCK_NS_MIN) {
       if (flags & 2) {
         const BlockOut bo{{w.grp[0].S, w.grp[1].S}, w.Dinv, w.group_c, w.diag, w.sur.J, ddfail_counter(w.flags),
-                          w.flags + FL_SURR_OFF, w.flags + FL_SING};
+                          w.flags + FL_SURR_OFF, w.flags + FL_SING, nullptr, 0};
         if (sur_ready) {
           const hipError_t e = hipStreamWaitEvent(st, sur_ready, 0);
           if (e != hipSuccess) return e;
@@ -152,10 +154,19 @@ template <int NS, int NT> class Runner : public IRunner {
     return hipGetLastError();
   }
 
-  hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc) override {
+  hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc, int flags) override {
     hipError_t e = prim(g, w, st, false, false);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sample<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, xr, jc);
+    hipLaunchKernelGGL((k_sample<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, xr, jc,
+                       flags);
+    if constexpr (NS >= BLOCK_NS_MIN) {
+      // the species rows from the block kernel (one lane per row)
+      hipLaunchKernelGGL((k_handoff<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, w.diag);
+      BlockOut bo{{nullptr, nullptr}, nullptr, 0, w.diag, nullptr, nullptr, nullptr, nullptr, jc, long(n)};
+      constexpr int C = BlockDims<NS, NT, 1>::C;
+      hipLaunchKernelGGL((k_block<NS, NT, float, 1>), dim3(nblocks(n, C)), dim3(64), 0, st, g, w.mech, w.Q, w.prim,
+                         2 | (flags & 24), bo, nullptr);
+    }
     return hipGetLastError();
   }
 
@@ -214,7 +225,8 @@ template <int NS, int NT> class Runner : public IRunner {
       else launch_pair<RT, 1>(g, a, gr, bl, st, done, mid);
       return hipGetLastError();
     }
-    SweepArgs a{w.prim, w.Ri, w.Rj, w.Dinv, w.b, w.dqs, w.dq, mode};
+    SweepArgs a{w.prim, w.Ri, w.Rj, w.Dinv, w.b, w.dqs, w.dq, mode, w.Q, w.fdiff ? w.mech : nullptr,
+                w.flags + FL_BAD};
     const int K = g.ni + g.nj - 1;
     for (int k = 0; k < K; ++k) {
       int j0 = k - g.ni + 1 > 0 ? k - g.ni + 1 : 0, j1 = k < g.nj - 1 ? k : g.nj - 1;

@@ -27,7 +27,7 @@ __device__ inline double sur_feature(const double *__restrict__ prim, size_t NP,
 template <int NS, int NT>
 __global__ void __launch_bounds__(256) k_sample(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
                                                 const double *__restrict__ prim, int n, float *__restrict__ xr,
-                                                float *__restrict__ jc) {
+                                                float *__restrict__ jc, int flags) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const Mech &m = *mech;
@@ -37,15 +37,30 @@ __global__ void __launch_bounds__(256) k_sample(Geo g, const Mech *__restrict__ 
   constexpr int NIN = NS + 3;
 #pragma unroll
   for (int k = 0; k < NIN; ++k) xr[long(p) * NIN + k] = float(sur_feature<NS, NT>(prim, NP, pc, k));
-  double rs[NS];
+  // the block kernel writes J_C where it builds the species blocks
+  if (NS >= BLOCK_NS_MIN) return;
+  constexpr int NV = Dims<NS, NT>::nv;
+  double q[NV];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) rs[s] = Q[size_t(s) * g.N + p];
+  for (int k = 0; k < NV; ++k) q[k] = Q[size_t(k) * g.N + p];
+  const double T = prim[F_T * NP + pc], Tv = prim[F_TV * NP + pc];
   Chem<NS, NT> C;
-  chemistry<NS, NT, true>(m, rs, prim[F_T * NP + pc], prim[F_TV * NP + pc], prim[F_P * NP + pc], C);
+  chemistry<NS, NT, true>(m, q, T, Tv, prim[F_P * NP + pc], C);
+  double dTc[NS], dTvc[NS];
+  if (flags & 8) {
+    Prim<NS, NT> P;
+    prim_from_q<NS, NT>(m, q, P, T, Tv);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) temp_derivs_fixed_e<NS, NT>(m, P, c, (flags & 16) != 0, dTc[c], dTvc[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < NS; ++c) dTc[c] = dTvc[c] = 0.0;
+  }
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
-    for (int r = 0; r < NS; ++r) jc[long(p) * NS * NS + s * NS + r] = float(C.dw_dr[s][r]);
+    for (int r = 0; r < NS; ++r)
+      jc[long(p) * NS * NS + s * NS + r] = float(C.dw_dr[s][r] + C.dw_dT[s] * dTc[r] + C.dw_dTv[s] * dTvc[r]);
 }
 
 // One block = 64 cells (4 waves x 16); J = sinh(y) / tau0.

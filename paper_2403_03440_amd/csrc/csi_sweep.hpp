@@ -81,7 +81,74 @@ struct SweepArgs {
   const void *Dinv, *b;
   void *xs, *x;
   int mode;
+  // flux-difference off-diagonal operator (FP64 sweeps): the state, the
+  // mechanism, and the flag receiving the first cell whose neighbour state
+  // plus increment is not physical (null: linear Jacobian-vector products)
+  const double *Q;
+  const Mech *mech;
+  int *bad;
 };
+
+// physical flux F(q).n of a state in the coupled unknowns' rows
+// (sum_s rho_s u_n, rho u u_n + p n_x, rho v u_n + p n_y, (rho E + p) u_n,
+// [rho e_ve u_n], rho_s u_n for s < ns - 1); flow part: the first nf rows
+template <int NS, int NT>
+__device__ __forceinline__ void flux_z(const double *q, double rho, double u, double v, double p, double nx,
+                                       double ny, double *f) {
+  using D = Dims<NS, NT>;
+  constexpr int NF = D::nf;
+  const double un = u * nx + v * ny;
+  f[0] = rho * un;
+  f[1] = q[NS] * un + p * nx;
+  f[2] = q[NS + 1] * un + p * ny;
+  f[3] = (q[NS + 2] + p) * un;
+  if (NT == 2) f[4] = q[NS + 3] * un;
+#pragma unroll
+  for (int k = 0; k < NS - 1; ++k) f[NF + k] = q[k] * un;
+}
+
+// Flux difference F(Q_N + x).n - F(Q_N).n, the nonlinear matrix-free
+// alternative to A_N(n) x: coupled (x in z) or flow part (x in Q_F at frozen
+// mass fractions).  False if Q_N + x is not a physical state.
+template <int NS, int NT>
+__device__ __forceinline__ bool flux_difference(const Geo &g, const SweepArgs &a, int pcN, int cN, int mode,
+                                                double nx, double ny, const double *x, double *o) {
+  using D = Dims<NS, NT>;
+  constexpr int NV = D::nv, NF = D::nf;
+  const Mech &m = *a.mech;
+  const size_t NP = g.NP;
+  double q0[NV], q1[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) q0[k] = a.Q[size_t(k) * g.N + cN];
+  double rho0 = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rho0 += q0[s];
+  if (mode == 0) {
+    double last = x[0];
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s) {
+      q1[s] = q0[s] + x[NF + s];
+      last -= x[NF + s];
+    }
+    q1[NS - 1] = q0[NS - 1] + last;
+  } else {
+    const double f = (rho0 + x[0]) / rho0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) q1[s] = q0[s] * f;
+  }
+#pragma unroll
+  for (int k = 0; k < NF - 1; ++k) q1[NS + k] = q0[NS + k] + x[1 + k];
+  Prim<NS, NT> P1;
+  if (!prim_from_q<NS, NT>(m, q1, P1, a.prim[F_T * NP + pcN], a.prim[F_TV * NP + pcN])) return false;
+  double f0[D::nb], f1[D::nb];
+  flux_z<NS, NT>(q0, rho0, a.prim[F_U * NP + pcN], a.prim[F_V * NP + pcN], a.prim[F_P * NP + pcN], nx, ny, f0);
+  flux_z<NS, NT>(q1, P1.rho, P1.u, P1.v, P1.p, nx, ny, f1);
+  const int n = mode == 0 ? D::nb : NF;
+#pragma unroll
+  for (int k = 0; k < D::nb; ++k)
+    if (k < n) o[k] = f1[k] - f0[k];
+  return true;
+}
 
 // apply O_PN to the neighbour increment(s) and accumulate with sign sg into r
 template <int NS, int NT, typename RT>
@@ -103,17 +170,41 @@ __device__ __forceinline__ void off_accumulate(const Geo &g, const SweepArgs &a,
     RT x[NB], o[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) x[k] = X[size_t(k) * g.N + cN];
-    jvp_coupled<NS, NT, RT>(s, nx, ny, x, o);
+    if constexpr (sizeof(RT) == 8) {
+      if (a.mech) {
+        if (!flux_difference<NS, NT>(g, a, pcN, cN, 0, nx, ny, x, o)) {
+          atomicMin(a.bad, cN);
+#pragma unroll
+          for (int k = 0; k < NB; ++k) o[k] = 0.0;
+        }
+      } else {
+        jvp_coupled<NS, NT, RT>(s, nx, ny, x, o);
+      }
+    } else {
+      jvp_coupled<NS, NT, RT>(s, nx, ny, x, o);
+    }
     RT lv = RT(Rr[size_t(R_LVK) * nfc + f]);
 #pragma unroll
     for (int k = 0; k < NB; ++k) r[k] += sg * (half * S * (o[k] - lam * x[k]) - lv * S * x[k]);
   } else {
     NbState<NS, RT> s;
     load_nb<NS, NT, RT, 1>(a.prim, NP, pcN, s);
-    RT x[NF], o[NF];
+    RT x[NF], o[D::nb];
 #pragma unroll
     for (int k = 0; k < NF; ++k) x[k] = X[size_t(k) * g.N + cN];
-    jvp_flow<NS, NT, RT>(s, nx, ny, x, o);
+    if constexpr (sizeof(RT) == 8) {
+      if (a.mech) {
+        if (!flux_difference<NS, NT>(g, a, pcN, cN, 1, nx, ny, x, o)) {
+          atomicMin(a.bad, cN);
+#pragma unroll
+          for (int k = 0; k < NF; ++k) o[k] = 0.0;
+        }
+      } else {
+        jvp_flow<NS, NT, RT>(s, nx, ny, x, o);
+      }
+    } else {
+      jvp_flow<NS, NT, RT>(s, nx, ny, x, o);
+    }
     RT lvF = RT(Rr[size_t(R_LVF) * nfc + f]);
 #pragma unroll
     for (int k = 0; k < NF; ++k) r[k] += sg * (half * S * (o[k] - lam * x[k]) - lvF * S * x[k]);

@@ -6,7 +6,7 @@ errors."""
 import numpy as np
 import pytest
 
-from gpu_cases import groups_inc, groups_state, make_pair_evolved, normwise, oracle_noise
+from gpu_cases import groups_inc, groups_state, make_pair_evolved, mech_by_name, normwise, oracle_noise, pair
 
 pytestmark = pytest.mark.gpu
 
@@ -80,7 +80,7 @@ def test_dual_time_short_run():
 
 def test_dual_time_argument_errors():
     csi = _csi()
-    m, o, s, q0 = make_pair_evolved("air5_1T", 8, 6)
+    o, s, q0 = pair(mech_by_name("air5_1T"), 8, 6, seed=3, T_range=(300.0, 1200.0), speed=800.0)
     with pytest.raises(csi.CsiError, match="CSI_ERR_ARG"):
         s.set_physical_time(-1.0, 0.0)
     with pytest.raises(csi.CsiError, match="CSI_ERR_ARG"):

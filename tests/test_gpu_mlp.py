@@ -179,25 +179,32 @@ def _features_oracle(o, m):
     return mlp.features(T, Tv if m.two_temp else T, rho, (q[:m.ns] / rho).T)
 
 
-@pytest.mark.parametrize("name", ["air5_2T", "air11_2T", "air5_1T"])
-def test_sample_jacobians_parity(name):
-    print(f"sample {name}", flush=True)
+@pytest.mark.parametrize("name", ["air5_2T", "air11_2T", "air5_1T", "syn20_1T", "toy2_1T"])
+@pytest.mark.parametrize("reading", [0, 1, 2])
+def test_sample_jacobians_parity(name, reading):
+    print(f"sample {name} reading {reading}", flush=True)
     torch = _torch()
     m = mech_by_name(name)
     o, s, q0 = pair(m, 32, 24, state="evolved", mech_name=name, iters=40)
+    o.set_option("jc_fixed_qf", reading + 1 if reading else 0)
+    s.set_species_jacobian(reading)
     o.residual(10.0)
     N = s.N
     xr = torch.empty((N, m.ns + 3), dtype=torch.float32, device="cuda")
     jc = torch.empty((N, m.ns * m.ns), dtype=torch.float32, device="cuda")
     assert s.sample_jacobians(xr, jc) == N
     xo = _features_oracle(o, m)
-    assert normwise(xr.cpu().numpy().T, xo.T).max() <= 1e-6
+    # the mass fractions share one scale (trace species fall below FP32's range)
+    fg = [[0], [1], [2], list(range(3, m.ns + 3))]
+    assert normwise(xr.cpu().numpy().T, xo.T, fg).max() <= 1e-6
     Jo = o.get("JC").transpose(2, 0, 1).reshape(N, -1)       # (s, r) row-major per cell
     Jg = jc.cpu().numpy().astype(np.float64)
     scale = np.abs(Jo).max(axis=1, keepdims=True) + 1e-300
     assert np.all(np.abs(Jg - Jo) <= 1e-6 * scale)
     n = s.sample_jacobians(xr, jc, max_samples=100)
     assert n == 100
+    Jg100 = jc[:100].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Jg100 - Jo[:100]) <= 1e-6 * scale[:100])
 
 
 def _oracle_scales(o, m):

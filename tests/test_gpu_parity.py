@@ -317,23 +317,26 @@ def test_strip_ragged(ni, nj, w):
         assert np.all(normwise(s.get("dq", mode), o.get("dq", mode), g) <= np.maximum(TOL64, 10.0 * noise))
 
 
-@pytest.mark.parametrize("name,ni,nj", [("air5_1T", 32, 24), ("air5_2T", 32, 24), ("air11_2T", 32, 24),
-                                        ("syn20_1T", 32, 24)])
-def test_species_jacobian_fixed_internal_energy_parity(name, ni, nj):
+@pytest.mark.parametrize("name,ni,nj,reading", [("air5_1T", 32, 24, 1), ("air5_2T", 32, 24, 1), ("air11_2T", 32, 24, 1),
+                                                ("syn20_1T", 32, 24, 1), ("toy2_1T", 24, 16, 1),
+                                                ("air5_2T", 32, 24, 2), ("air11_2T", 32, 24, 2),
+                                                ("toy3_2T", 7, 5, 2)])
+def test_species_jacobian_fixed_internal_energy_parity(name, ni, nj, reading):
     """Split increments with the species block at fixed velocities and
     internal energy densities (csi_set_species_jacobian(ctx, 1)) against the
     oracle's complex-step Jacobian of the same reading; FP64 to the bar of
     test_implicit_op_parity, mixed precision to 2e-5; and the reading does
     change the increment."""
-    print(f"case {name} {ni}x{nj} species Jacobian at fixed internal energy", flush=True)
+    print(f"case {name} {ni}x{nj} species Jacobian at fixed internal energy, reading {reading}", flush=True)
     csi = _csi()
-    m, (o, s, q0) = make_pair(name, ni, nj, "evolved", seed=5)
+    m, (o, s, q0) = make_pair(name, ni, nj, "random" if name == "toy3_2T" else "evolved", seed=5)
     g = groups_inc(m, 1)
+    s.set_species_jacobian(0)      # the fixed-temperature block first, for the comparison below
     s.residual(10.0)
     s.implicit_op(csi.SPLIT, csi.FP64)
     dq_t = s.get("dq", 1)
-    o.set_option("jc_fixed_qf", 2)
-    s.set_species_jacobian(1)
+    o.set_option("jc_fixed_qf", reading + 1)
+    s.set_species_jacobian(reading)
     noise = oracle_noise(o, q0, 1, 10.0, g)
     s.residual(10.0)
     s.implicit_op(csi.SPLIT, csi.FP64)
@@ -351,7 +354,37 @@ def test_species_jacobian_fixed_internal_energy_parity(name, ni, nj):
 def test_species_jacobian_reading_errors():
     csi = _csi()
     m, (o, s, q0) = make_pair("toy2_1T", 8, 6, "random")
-    with pytest.raises(csi.CsiError, match="CSI_ERR_UNSUPPORTED"):
-        s.set_species_jacobian(1)      # per-thread blocks (ns < 5) keep the fixed-temperature reading
     with pytest.raises(csi.CsiError, match="CSI_ERR_ARG"):
-        s.set_species_jacobian(2)
+        s.set_species_jacobian(3)
+
+
+@pytest.mark.parametrize("name,ni,nj", [("air5_1T", 32, 24), ("air5_2T", 32, 24), ("air11_2T", 32, 24),
+                                        ("syn20_1T", 32, 24), ("toy2_1T", 24, 16)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_flux_difference_parity(name, ni, nj, mode):
+    """Sweeps with the flux-difference off-diagonal operator F(Q_N + x) -
+    F(Q_N) (csi_set_offdiag(ctx, 1): per-hyperplane schedule, FP64) against
+    the oracle's, to the bar of test_implicit_op_parity; the increment differs
+    from the linear operator's."""
+    print(f"case {name} {ni}x{nj} mode {mode} flux difference", flush=True)
+    csi = _csi()
+    m, (o, s, q0) = make_pair(name, ni, nj, "evolved", seed=5)
+    g = groups_inc(m, mode)
+    s.residual(10.0)
+    s.implicit_op(mode, csi.FP64)
+    d_lin = s.get("dq", mode)
+    o.set_option("flux_diff", 1)
+    s.set_offdiag(1)
+    noise = oracle_noise(o, q0, mode, 10.0, g)
+    s.residual(10.0)
+    s.implicit_op(mode, csi.FP64)
+    e = normwise(s.get("dq", mode), o.get("dq", mode), g)
+    tol = np.maximum(TOL64, 10.0 * noise)
+    print("err", e.max(), "oracle noise", noise.max(), "tol", tol.max(), flush=True)
+    assert np.all(tol <= 1e-9), noise
+    assert np.all(e <= tol), (e, noise)
+    assert normwise(s.get("dq", mode), d_lin, g).max() > 1e3 * tol.max()
+    s.residual(10.0)
+    with pytest.raises(csi.CsiError, match="CSI_ERR_UNSUPPORTED"):
+        s.implicit_op(mode, csi.MIXED)
+    o.set_option("flux_diff", 0)

@@ -450,7 +450,8 @@ def test_species_jacobian_fixed_internal_energy(name):
     through the energies, written out here: dT/d rho_r = -(e_r - e_ve,r) /
     (rho c_v,tr) and dTv/d rho_r = -e_ve,r / (rho c_v,ve) in two temperatures,
     dT/d rho_r = -e_r / (rho c_v) in one; every derivative of the production
-    rates by central differences of the point rates."""
+    rates by central differences of the point rates.  The third reading (two
+    temperatures: Tv held as well) gives dT/d rho_r = -e_r / (rho c_v,tr)."""
     m = {"air5_1T": lambda: I.air5(0), "syn20_1T": lambda: I.synthetic(20, 60, 3442),
          "air5_2T": lambda: I.air5(1)}[name]()
     x, y = I.polar_grid(4, 3)
@@ -459,6 +460,11 @@ def test_species_jacobian_fixed_internal_energy(name):
     o = orc.setup((x, y), m, (1e-3 * Y, 5000.0, 0.0, 250.0, 250.0))
     q = o.prim_to_cons(*I.random_prims(m, 12, 11, T_range=(2500.0, 7000.0), speed=3000.0, y_floor=0.01))
     o.set_state(q)
+    JC3s = None
+    if m.two_temp:
+        o.set_option("jc_fixed_qf", 3)
+        o.residual(10.0)
+        JC3s = o.get("JC")
     o.set_option("jc_fixed_qf", 2)
     o.residual(10.0)
     JC = o.get("JC")
@@ -490,3 +496,7 @@ def test_species_jacobian_fixed_internal_energy(name):
         assert err <= 2e-6, (p, err)
         # and the temperature term is not negligible here
         assert np.abs(J - JT).max() >= 1e-3 * np.abs(J).max()
+        if m.two_temp:
+            JC3 = JC3s[:, :, p]
+            J3 = JT + np.outer(dwdT, -e / (rs @ cv0))   # Tv held: T takes all of the added e_r
+            assert np.abs(JC3 - J3).max() <= 2e-6 * np.abs(J3).max(), p
