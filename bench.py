@@ -25,6 +25,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -388,11 +389,13 @@ def workload_text(cfg, m):
             f"iterations), uniform free-stream start")
 
 
-def tol_leg(csi, I, name, names, tol, max_iter, epochs, snapshots):
+def tol_leg(csi, I, name, names, tol, max_iter, epochs, snapshots, ramp=0):
     """Every variant from the free stream to the tolerance on one workload,
     the converged states against the split FP64 run's, and the surrogate's
     amortised cost (sampling + training + solve) against the exact block."""
     cfg = I.CONFIGS[name]
+    if ramp:
+        cfg = dataclasses.replace(cfg, ramp=ramp)
     m = cfg.mechanism()
     x, y = cfg.grid()
     fs = I.freestream_prims(cfg, m)
@@ -424,9 +427,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--variants", default="splitmixed_mlp,splitmixed,split64,coupled64,coupledmixed")
-    ap.add_argument("--epochs", type=int, default=0, help="surrogate training epochs (0: 5 on c5, else 20)")
+    ap.add_argument("--epochs", type=int, default=0, help="surrogate training epochs (0: 20)")
     ap.add_argument("--snapshots", type=int, default=0,
-                    help="surrogate training snapshots, all cells each (0: 2 on c5, else 16)")
+                    help="surrogate training snapshots, all cells each (0: 4 on c5, else 16)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=12000)
     ap.add_argument("--converge", action="store_true", help="also run every variant to the tolerance on --config")
@@ -434,6 +437,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--species-jacobian", type=int, default=0,
                     help="split species block: 0 fixed T, Tv; 1 fixed velocities and internal energy")
+    ap.add_argument("--ramp", type=int, default=0, help="CFL ramp length in iterations (0: the workload's own)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--scaling", default="", help="species counts (e.g. 5,11,16,20,32): implicit-step time vs ns "
                                                  "in non-reacting flow, instead of the workload above")
@@ -450,9 +454,11 @@ def main():
         print(json.dumps(scaling(csi, I, [int(v) for v in args.scaling.split(",")], args.steps, args.warmup)))
         return
     cfg = I.CONFIGS[args.config]
+    if args.ramp:
+        cfg = dataclasses.replace(cfg, ramp=args.ramp)
     big = cfg.ni * cfg.nj > 1_000_000
-    epochs = args.epochs or (5 if big else 20)
-    snapshots = args.snapshots or (2 if big else 16)
+    epochs = args.epochs or 20
+    snapshots = args.snapshots or (4 if big else 16)
     m = cfg.mechanism()
     x, y = cfg.grid()
     fs = I.freestream_prims(cfg, m)
@@ -503,7 +509,7 @@ def main():
         out["speedup_vs_coupled64"] = {v: r["cell_iters_per_s"] / res["coupled64"]["cell_iters_per_s"]
                                        for v, r in res.items()}
     if args.tol_config:
-        out["time_to_tol"] = tol_leg(csi, I, args.tol_config, names, args.tol, args.max_iter, 20, 16)
+        out["time_to_tol"] = tol_leg(csi, I, args.tol_config, names, args.tol, args.max_iter, 20, 16, args.ramp)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(I, cfg, m)

@@ -322,6 +322,15 @@ int csi_mlp_grad(csi_ctx *ctx, const csi_mlp_batch *b, float *grad, double *loss
 int csi_mlp_train_step(csi_ctx *ctx, const csi_mlp_batch *b, float *m, float *v, int step, const csi_adam *h,
                        double *loss);
 
+/* One epoch: Adam steps (as csi_mlp_train_step) over the rows order[0..n_rows)
+ * (device int array, each a row of b->x / b->t) taken b->batch at a time, the
+ * last batch possibly shorter; steps are numbered step0 + 1, step0 + 2, ...
+ * (b->idx is not used).  Launches only, except that the host waits for loss
+ * (host, nullable): the mean squared error of the last batch before its
+ * update.  Errors: CSI_ERR_ARG for bad sizes, pointers or Adam arguments. */
+int csi_mlp_train_epoch(csi_ctx *ctx, const csi_mlp_batch *b, const int *order, int n_rows, float *m, float *v,
+                        int step0, const csi_adam *h, double *loss);
+
 /* Training samples from the bound state: for cells 0..n-1 (n = min(N,
  * max_samples), returned in *n_written) the raw features x_raw [n][ns + 3] and
  * the exact J_C [n][ns * ns] (FP32) of the species block's reading

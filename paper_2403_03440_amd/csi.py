@@ -33,7 +33,7 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
             "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate", "csi_mlp_forward_noalloc",
             "csi_set_species_jacobian", "csi_set_physical_time", "csi_advance_time",
-            "csi_set_time_levels", "csi_set_offdiag"]
+            "csi_set_time_levels", "csi_set_offdiag", "csi_mlp_train_epoch"]
 PHASES = ["prim", "faces", "cell", "block", "norms", "sweep_fwd", "sweep_bwd", "update"]
 
 
@@ -399,6 +399,17 @@ class Mlp:
         b = self._batch(params, x, t, idx)
         self._check(self.L.csi_mlp_grad(self.ctx, C.byref(b), self._p(g), C.byref(loss)))
         return g, loss.value
+
+    def train_epoch(self, params, m, v, x, t, order, step0, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam steps over the device row order `order` (int32), self.batch rows
+        at a time; returns the last batch's loss."""
+        b = self._batch(params, x, t, order[:min(self.batch, order.numel())])
+        b.batch = self.batch
+        h = Adam(lr, beta1, beta2, eps)
+        loss = C.c_double(0)
+        self._check(self.L.csi_mlp_train_epoch(self.ctx, C.byref(b), self._p(order), int(order.numel()),
+                                               self._p(m), self._p(v), int(step0), C.byref(h), C.byref(loss)))
+        return loss.value
 
     def train_step(self, params, m, v, x, t, idx, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                    want_loss=True):

@@ -1029,7 +1029,13 @@ int csi_get_array(csi_ctx *c, const char *name, double *out, size_t count) {
     std::vector<float> tmp(cntj);
     int rc = hip_check(c, hipMemcpy(tmp.data(), c->w.sur.J, cntj * 4, hipMemcpyDeviceToHost), "get");
     if (rc) return rc;
-    for (size_t k = 0; k < cntj; ++k) out[k] = tmp[k];
+    const size_t nn = size_t(c->ns) * c->ns;
+    if (c->ns >= BLOCK_NS_MIN) {  // stored cell-major for the block kernel
+      for (size_t p = 0; p < size_t(N); ++p)
+        for (size_t k = 0; k < nn; ++k) out[k * N + p] = tmp[p * nn + k];
+    } else {
+      for (size_t k = 0; k < cntj; ++k) out[k] = tmp[k];
+    }
     return CSI_OK;
   } else if (n == "T" || n == "Tv" || n == "p" || n == "c") {
     int fld = n == "T" ? F_T : n == "Tv" ? F_TV : n == "p" ? F_P : F_C;
@@ -1217,6 +1223,28 @@ int csi_mlp_train_step(csi_ctx *c, const csi_mlp_batch *b, float *m, float *v, i
       !(h->beta2 >= 0.0 && h->beta2 < 1.0) || !(h->eps > 0.0))
     return c->fail(CSI_ERR_ARG, "mlp_train_step: Adam arguments");
   return mlp_grad_adam(c, b, nullptr, m, v, step, h, loss);
+}
+
+int csi_mlp_train_epoch(csi_ctx *c, const csi_mlp_batch *b, const int *order, int n_rows, float *m, float *v,
+                        int step0, const csi_adam *h, double *loss) {
+  if (!c) return CSI_ERR_ARG;
+  if (!b || !order || n_rows < 1 || b->batch < 1 || step0 < 0)
+    return c->fail(CSI_ERR_ARG, "mlp_train_epoch: arguments");
+  if (!m || !v || !h || !(h->lr > 0.0) || !(h->beta1 >= 0.0 && h->beta1 < 1.0) ||
+      !(h->beta2 >= 0.0 && h->beta2 < 1.0) || !(h->eps > 0.0))
+    return c->fail(CSI_ERR_ARG, "mlp_train_epoch: Adam arguments");
+  // every step's kernels go on the stream back to back; the host waits only
+  // for the last batch's loss
+  csi_mlp_batch lb = *b;
+  int step = step0;
+  for (long b0 = 0; b0 < n_rows; b0 += b->batch) {
+    const bool last = b0 + b->batch >= n_rows;
+    lb.idx = order + b0;
+    lb.batch = int(last ? n_rows - b0 : b->batch);
+    int rc = mlp_grad_adam(c, &lb, nullptr, m, v, ++step, h, last ? loss : nullptr);
+    if (rc) return rc;
+  }
+  return CSI_OK;
 }
 
 int csi_sample_jacobians(csi_ctx *c, int max_samples, float *x_raw, float *jc, int *n_written) {

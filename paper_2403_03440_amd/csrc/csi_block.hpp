@@ -34,7 +34,7 @@ struct BlockOut {
   void *Dinv;                  // hyperplane schedule: cell-major inverses (layout as the cell kernel's)
   int group_c;                 // 0: hyperplane schedule; > 0: group schedule
   const double *hb;            // [hb_fields][N] from the cell kernel
-  const float *Jsur;           // surrogate J_C [ns * ns][N]
+  const float *Jsur;           // surrogate J_C, cell-major [N][ns][ns]
   unsigned long long *ddfail;  // cells whose surrogate block failed the dominance check
   const int *surr_off;         // >= 0: surrogate switched off
   int *bad;                    // first singular cell
@@ -182,6 +182,69 @@ __device__ __forceinline__ bool group_invert(double *scr, int *pv, int k, bool l
   return ok;
 }
 
+// The same inversion as group_invert (pivot order, pivot keys, result layout
+// and zero-pivot test alike) with fewer operations per column, used for the
+// split species block (at the coupled block's width its larger register
+// footprint costs a wave per SIMD).  B = P A is inverted in place, one column
+// per step, without
+// normalising the pivot row: the pivot lane publishes its row unchanged
+// (entry kc then set to 1), every other row subtracts g = b_ik / b_kk times
+// it (its entry kc becomes -g); a row that was pivot is p times the
+// normalised one for its own pivot value p, and the later steps keep that
+// factor, so each lane divides its row by its own pivot value at the end.
+// Per column and lane: one multiply-add per entry; only the pivot lanes
+// store a row.  On return lane k holds row pos of B^-1 = A^-1 P^T, i.e.
+// A[r] = (A^-1)[pos][piv(r)], where piv(r), the lane chosen at step r, is
+// left in pv[r].  The keys and the pivot rows go through the group's LDS
+// (scr: [G][G] rows, then G keys).  False on a zero pivot (the group agrees).
+template <int G>
+__device__ __forceinline__ bool group_invert_unnormalised(double *scr, int *pv, int k, bool live, double (&A)[G], int &pos) {
+  static_assert(G <= 64, "lane index in 6 bits");
+  double *rows = scr;
+  unsigned *keys = reinterpret_cast<unsigned *>(scr + G * G);
+  pos = -1;
+  bool ok = true;
+  double myip = 1.0;
+#pragma unroll
+  for (int kc = 0; kc < G; ++kc) {
+    const double f = A[kc];
+    const float a = float(fabs(f));
+    const unsigned mag = __float_as_uint(a >= 0.0f ? a : 0.0f) & ~63u;
+    const unsigned key = pos >= 0 ? 0u : ((mag > 64u ? mag : 64u) | unsigned(63 - k));
+    if (live) keys[k] = key;
+    wave_sync();
+    unsigned best = 0u;
+    for (int j = 0; j < G; ++j) best = keys[j] > best ? keys[j] : best;
+    if ((best >> 6) <= 1u) ok = false;  // the pivot is zero (or below FP32's range)
+    const int piv = 63 - int(best & 63u);
+    const bool me = k == piv;
+    if (me) pos = kc;
+    if (live) pv[kc] = piv;
+    // the pivot lane of each group publishes its row (the others store nothing)
+    if (me && live) {
+#pragma unroll
+      for (int c = 0; c < G; ++c) rows[k * G + c] = A[c];
+    }
+    wave_sync();
+    const double *pr = rows + piv * G;
+    const double ip = 1.0 / pr[kc];
+    const double gk = me ? 0.0 : f * ip;
+    if (me) myip = ip;
+    // the pivot row in chunks of eight (a scheduling fence between chunks
+    // keeps the compiler from holding the whole row in registers at once)
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const double r = pr[c];
+      A[c] = c == kc ? (me ? 1.0 : -gk) : fma(-gk, r, A[c]);
+      if (c % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < G; ++c) A[c] *= myip;
+  wave_sync();
+  return ok;
+}
+
 // Record of reaction r at (T, Tv) into D[RW] (the same kinetics as
 // `chemistry`): D[u] = (dq_r / dX_u) / M_u (third-body efficiencies and the
 // law-of-mass-action products), D[NS] = q_r, D[NS+1] = dq_r/dT, D[NS+2] =
@@ -307,7 +370,12 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
   // stage the hand-off; lane s evaluates species s's Gibbs energy and enthalpy
   const double lnT = log(T), lnTv = log(Tv);
   if (live) {
-    for (int f = k; f < BD::NHB; f += G) buf[f] = out.hb[size_t(HB_X + f) * g.N + p];
+    for (int f = k; f < BD::NHB; f += G) {
+      // one temperature: the dTv/dq row is not handed over (its derivatives
+      // enter with the zero dq/dTv of the reaction records)
+      const bool tv_row = f >= NS + NV && f < NS + 2 * NV;
+      buf[f] = NT == 1 && tv_row ? 0.0 : out.hb[size_t(HB_X + f) * g.N + p];
+    }
     if (k < NS) {
       GH[k] = gRT(m, k, T, lnT);
       GH[NS + k] = hRT2(m, k, T);
@@ -327,7 +395,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     double off = 0.0, dkk = 0.0;
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
-      const double a = (c == k ? d1 : 0.0) - Vp * double(out.Jsur[size_t(tc * NS + c) * g.N + p]);
+      const double a = (c == k ? d1 : 0.0) - Vp * double(out.Jsur[(size_t(p) * NS + tc) * NS + c]);
       if (c == k) dkk = a;
       else off += fabs(a) * m.M[c];
     }
@@ -349,32 +417,13 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
       if (live && r0 + k < m.nr) reaction_record<NS, NT>(m, r0 + k, T, Tv, lnT, lnTv, lnc0, X, GH, scr + k * RW);
       wave_sync();
       const int nk = m.nr - r0 < G ? m.nr - r0 : G;
-      // the chunk's reactions that change this lane's species: bit kk of
-      // `mask`, their net coefficients packed three bits each, ten per word;
-      // each lane then visits only its own reactions, in ascending order
-      constexpr int NW = (G + 9) / 10;
-      unsigned long long mask = 0ull;
-      unsigned pk[NW];
+      double av[G];  // M_t nu_tr of the chunk's reactions, loaded together
 #pragma unroll
-      for (int w = 0; w < NW; ++w) pk[w] = 0u;
+      for (int kk = 0; kk < G; ++kk) av[kk] = t >= 0 && kk < nk ? m.nuM[r0 + kk][tc] : 0.0;
 #pragma unroll
       for (int kk = 0; kk < G; ++kk) {
-        const int v = live && t >= 0 && kk < nk ? int(m.nu_net[r0 + kk][tc]) : 0;
-        if (v != 0) mask |= 1ull << kk;
-        pk[kk / 10] |= unsigned(v & 7) << (3 * (kk % 10));
-      }
-      const double Mt = m.M[tc];
-      while (__ballot(mask != 0ull) != 0ull) {
-        if (mask != 0ull) {
-          const int kk = __builtin_ctzll(mask);
-          mask &= mask - 1ull;
-          const int wsel = kk / 10;
-          unsigned wd = pk[0];
-#pragma unroll
-          for (int w = 1; w < NW; ++w) wd = wsel == w ? pk[w] : wd;
-          int v = int((wd >> (3 * (kk - 10 * wsel))) & 7u);
-          v = v >= 4 ? v - 8 : v;
-          const double a = Mt * double(v);  // M_t nu_tr
+        const double a = av[kk];
+        if (kk < nk && a != 0.0) {
           const double *D = scr + kk * RW;
 #pragma unroll
           for (int u = 0; u < NS; ++u) row[u] += a * D[u];
@@ -496,7 +545,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     double jr[NS];
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
-      double jc = use_sur ? double(out.Jsur[size_t(tc * NS + c) * g.N + p]) : row[c];
+      double jc = use_sur ? double(out.Jsur[(size_t(p) * NS + tc) * NS + c]) : row[c];
       if (te) {
         const double ev = hold_tv ? buf[BD::O_EV + c] : 0.0;
         jc += dwT * (TQ[c] + uu * TQ[NS] + vv * TQ[NS + 1] + ke * TQ[NS + 2] + (NT == 2 ? ev * TQ[NS + 3] : 0.0));
@@ -551,7 +600,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
         for (int c = 0; c < 6; ++c) Dcm[long(c) * g.N + p] = RT(df6[c]);
       }
     }
-    ok = group_invert<G>(scr, pv, k, live, A, pos);
+    ok = group_invert_unnormalised<G>(scr, pv, k, live, A, pos);
     if (real) {
       if (out.group_c > 0) {
         constexpr RecShape S = rec_shape(PART_SPECIES, NS, NT, sizeof(RT));

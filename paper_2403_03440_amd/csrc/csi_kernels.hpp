@@ -475,8 +475,8 @@ __host__ __device__ inline long group_blk(const GroupMap &m, int i, int j, int &
 // mode 0: coupled (nb x nb block in z = rho, momenta, energies, rho_1..rho_{ns-1})
 // mode 1: split (flow block in closed form, ns x ns species block)
 // Per-cell hand-off from the cell kernel to k_block (fields from HB_X on,
-// [field][N]): X_s = rho_s / M_s, dT/dq_c, dTv/dq_c for every stored variable,
-// Y_s.
+// [field][N]): X_s = rho_s / M_s, dT/dq_c, dTv/dq_c for every stored variable
+// (two temperatures only), Y_s.
 template <int NS, int NT>
 __device__ __forceinline__ void write_handoff(const Mech &m, const double *rs, const Prim<NS, NT> &P, double *diag,
                                               long N, int p) {
@@ -492,7 +492,7 @@ __device__ __forceinline__ void write_handoff(const Mech &m, const double *rs, c
     double dT, dTv;
     temp_derivs<NS, NT>(P, c, dT, dTv);
     hb[size_t(NS + c) * N] = dT;
-    hb[size_t(NS + NV + c) * N] = dTv;
+    if (NT == 2) hb[size_t(NS + NV + c) * N] = dTv;  // one temperature: Tv is T, its row unused
   }
 }
 

@@ -57,7 +57,6 @@ inline bool build_mech(const csi_mechanism *mm, Mech &m, std::string &err) {
         R.prod[R.nprod++] = s;
       }
       m.nuM[r_][s] = mm->M[s] * double(nb_ - nf_);
-      m.nu_net[r_][s] = static_cast<signed char>(nb_ - nf_);
       if (nb_ != nf_) {
         R.net_s[R.nnet] = s;
         R.net_nu[R.nnet] = nb_ - nf_;

@@ -46,7 +46,6 @@ struct Mech {
   double mu_ref, T_ref, mu_exp;
   double iM[MAXS];          // 1 / M_s
   double nuM[MAXR][MAXS];   // M_s (nu''_rs - nu'_rs): weight of reaction r's rate in omega_s
-  signed char nu_net[MAXR][MAXS];  // nu''_rs - nu'_rs (at most 3 in magnitude)
 };
 
 template <int NS, int NT> struct Dims {

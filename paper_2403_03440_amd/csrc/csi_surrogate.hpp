@@ -88,12 +88,17 @@ __global__ void __launch_bounds__(256) k_surrogate(Geo g, const double *__restri
   u16x8 B2[2];
   mlp_hidden<KS1>(d, a.P, a.p, xin, h1, h2, B2);
   const double itau = 1.0 / a.scales[2 * NIN];
+  // layout of J: [ns * ns][N] where the cell kernel reads it (one thread per
+  // cell, ns < 5); cell-major [N][ns * ns] where the block kernel does (each
+  // lane reads one contiguous row of its cell's block)
+  constexpr bool CELL_MAJOR = NS >= BLOCK_NS_MIN;
   for (int t = 0; t < d.nt3; ++t) {
     f32x4 y = mlp_out_tile(d, a.P, a.p, B2, t);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int o = 16 * t + 4 * gq + r;
-      if (valid && o < NS * NS) a.J[size_t(o) * g.N + p] = float(sinh(double(y[r])) * itau);
+      const size_t at = CELL_MAJOR ? size_t(p) * (NS * NS) + o : size_t(o) * g.N + p;
+      if (valid && o < NS * NS) a.J[at] = float(sinh(double(y[r])) * itau);
     }
   }
 }

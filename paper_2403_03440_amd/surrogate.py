@@ -71,19 +71,16 @@ def train(x_raw, jc, epochs=20, batch=4096, lr=1e-3, seed=3441, holdout=0.1, log
     hist = []
     step = 0
     t0 = time.perf_counter()
+    tr_dev = torch.tensor(tr.astype(np.int64), device=x.device)
     for ep in range(epochs):
-        order = tr[I.permutation(seed + 2 + ep, tr.size)]
-        dev_order = torch.tensor(order, device=x.device)
-        tl = 0.0
-        nb = 0
-        for b0 in range(0, order.size, batch):
-            idx = dev_order[b0:b0 + batch]
-            step += 1
-            last = b0 + batch >= order.size
-            l_ = net.train_step(params, m, v, x, t, idx, step, lr=lr, want_loss=last)
-            if last:
-                tl = l_
-            nb += 1
+        # the seeded permutation of inputs.permutation, sorted on the device
+        keys = I.splitmix64(np.uint64(seed + 2 + ep) ^ np.arange(tr.size, dtype=np.uint64))
+        keys = torch.from_numpy((keys ^ np.uint64(1 << 63)).view(np.int64)).to(x.device)
+        dev_order = tr_dev[torch.argsort(keys, stable=True)].to(torch.int32)
+        # the whole epoch in one library call (kernels back to back on the stream)
+        tl = net.train_epoch(params, m, v, x, t, dev_order, step, lr=lr)
+        nb = -(-tr.size // batch)
+        step += nb
         vl = float("nan")
         if n_val:
             vl = 0.0

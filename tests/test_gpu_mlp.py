@@ -416,3 +416,25 @@ def test_trained_surrogate_reaches_the_same_steady_state():
     assert ss["n_dd_fallback"] <= 0.95 * ss["iters"] * s.N
     assert normwise(qs, qe, [list(range(m.ns)), [m.ns, m.ns + 1], [m.ns + 2], [m.ns + 3]]).max() <= 1e-6
     assert abs(qss - qse) <= 1e-6 * abs(qse)
+
+
+def test_train_epoch_equals_train_steps():
+    """csi_mlp_train_epoch (one call per epoch) takes the same Adam steps as
+    csi_mlp_train_step called per batch: the parameters and moments agree
+    bitwise, the last batch shorter than the others."""
+    torch = _torch()
+    csi = _csi()
+    n_in, n_out, n_data, batch = 14, 121, 1000, 96
+    p, x, t, _ = _emulated_grad_case(n_in, n_out, n_data, batch, 77)
+    order = I.permutation(5, n_data)[:700].astype(np.int32)     # 7 full batches and one of 28
+    net = csi.Mlp(n_in, n_out, batch=batch)
+    xd, td, od = _dev(x), _dev(t), _dev(order, torch.int32)
+    pa, ma, va = _dev(p), torch.zeros(p.size, device="cuda"), torch.zeros(p.size, device="cuda")
+    pb, mb, vb = _dev(p), torch.zeros(p.size, device="cuda"), torch.zeros(p.size, device="cuda")
+    step = 3
+    for b0 in range(0, order.size, batch):
+        step += 1
+        la = net.train_step(pa, ma, va, xd, td, od[b0:b0 + batch], step, lr=2e-3)
+    lb = net.train_epoch(pb, mb, vb, xd, td, od, 3, lr=2e-3)
+    assert torch.equal(pa, pb) and torch.equal(ma, mb) and torch.equal(va, vb)
+    assert la == lb
