@@ -40,7 +40,7 @@ enum {
   CSI_ERR_HIP = -3,       /* HIP runtime error */
   CSI_ERR_NONFINITE = -4, /* non-physical or non-finite state; cell index in stats / csi_bad_cell */
   CSI_ERR_SINGULAR = -5,  /* zero pivot in a diagonal block */
-  CSI_ERR_UNSUPPORTED = -6 /* species count / temperature model without a compiled kernel */
+  CSI_ERR_UNSUPPORTED = -6 /* species count / temperature model / feature without kernels for it */
 };
 enum { CSI_COUPLED = 0, CSI_SPLIT = 1 };
 enum { CSI_FP64 = 0, CSI_MIXED = 1 }; /* MIXED: FP32 blocks and sweeps; FP64 residual, chemistry, corrections */
@@ -115,9 +115,38 @@ int csi_set_grid(csi_ctx *ctx, int ni, int nj, const double *x_nodes, const doub
  * electronic energy with its source omega_ve; the thermodynamic, kinetic and
  * transport laws the paper defers to its references are fixed by the tables of
  * csi_mechanism).  The host tables are copied.  Compiled species counts: 2, 3,
- * 5 and 11 (one and two temperatures), 16, 20 and 32 (one temperature); others
- * return CSI_ERR_UNSUPPORTED; CSI_ERR_ARG for nr > 64 or bad tables. */
+ * 5 and 11 (one and two temperatures), 16, 20 and 32 (one temperature).  Any
+ * other count up to CSI_WIDE_MAX_SPECIES runs on the species-generic kernels,
+ * which take one temperature and no reactions (nr = 0: the non-reacting flow
+ * of the species-count study, Section 3.1); there the coupled form inverts
+ * its dense block by blocked Gauss-Jordan elimination, sweeps and block
+ * solves run in FP64 with per-hyperplane launches, and the surrogate,
+ * physical time and flux differences are not available (CSI_ERR_UNSUPPORTED).
+ * Errors: CSI_ERR_UNSUPPORTED for a species count with neither (two
+ * temperatures or reactions above 32 species); CSI_ERR_ARG for ns < 2, ns >
+ * CSI_WIDE_MAX_SPECIES, nr > 64 or bad tables. */
+#define CSI_WIDE_MAX_SPECIES 4096
 int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
+/* on = 1: the next csi_set_mechanism takes the species-generic kernels for
+ * every species count (so that they can be compared with the compiled ones on
+ * the same case); on = 0 (the default): only above 32 species.  Errors:
+ * CSI_ERR_ARG for another value. */
+int csi_set_species_generic(csi_ctx *ctx, int on);
+/* In-place inverse of `count` dense n x n FP64 matrices at a (device,
+ * row-major, contiguous; caller-owned): blocked Gauss-Jordan elimination with
+ * partial pivoting (largest magnitude in the pivot column among the rows not
+ * yet used, lowest row on ties), the coupled form's block solve of Section
+ * 2.2 (the diagonal point blocks of Eq. (ijkiterate)) on the species-generic
+ * path.  work: device scratch of at least csi_block_inverse_work(n, count)
+ * bytes, 256-byte aligned, caller-owned (row interchanges [count][n], pivot
+ * rows [count][64][n], a flag).  Runs on ctx's stream and synchronises it.
+ * *singular (optional) receives -1, or the lowest index of a matrix with a
+ * zero pivot (then CSI_ERR_SINGULAR; that matrix's contents are undefined, the
+ * others are inverted).  Errors: CSI_ERR_ARG for n < 1, n >
+ * CSI_WIDE_MAX_SPECIES + 3, count < 0, a null a with count > 0, or a missing,
+ * misaligned or short work buffer. */
+int csi_block_inverse_work(int n, int count, size_t *bytes);
+int csi_block_inverse(csi_ctx *ctx, int n, int count, double *a, void *work, size_t work_bytes, int *singular);
 /* Free-stream state of the far-field boundary (the Dirichlet far field of
  * Section 3; also the uniform flow of the Section 3.1 box) from primitives:
  * partial densities rho_s [ns] (host, copied), velocity (u, v), temperatures

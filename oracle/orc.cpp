@@ -829,7 +829,9 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
     // diagonal blocks (paper: I_m = (1/(J dtau)) I - A_S plus the split-radius diagonals)
     bool ok = true;
     {
-      double A[MAXV * MAXV];
+      thread_local std::vector<double> Abuf;
+      Abuf.resize(size_t(nb) * nb);
+      double *A = Abuf.data();
       int piv[MAXV];
       for (int r = 0; r < nb; ++r)
         for (int col = 0; col < nb; ++col)
@@ -852,7 +854,9 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
       for (int k = 0; k < nf; ++k) c->pivF[size_t(k) * N + p] = piv[k];
     }
     {
-      double A[MAXS * MAXS];
+      thread_local std::vector<double> Abuf;
+      Abuf.resize(size_t(ns) * ns);
+      double *A = Abuf.data();
       int piv[MAXS];
       for (int r = 0; r < ns; ++r)
         for (int col = 0; col < ns; ++col)
@@ -943,7 +947,9 @@ PartInfo part_info(orc_ctx *c, Part part, int mode) {
 
 void solve_block(orc_ctx *c, const PartInfo &pi, int p, double *x) {
   const int N = c->N, n = pi.n;
-  double A[MAXV * MAXV];
+  thread_local std::vector<double> Abuf;
+  Abuf.resize(size_t(n) * n);
+  double *A = Abuf.data();
   int piv[MAXV];
   for (int k = 0; k < n * n; ++k) A[k] = (*pi.LU)[size_t(k) * N + p];
   for (int k = 0; k < n; ++k) piv[k] = (*pi.piv)[size_t(k) * N + p];

@@ -12,6 +12,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the same sources with room for 256 species per cell (the species-count
+# study); the default build keeps 32 and with it smaller per-cell records
+WIDE_LIB_PATH = os.path.join(HERE, "liboracle_wide.so")
+WIDE_MAXS = 256
 SOURCES = ["orc.cpp", "orc_mlp.cpp"]
 
 COUPLED, SPLIT = 0, 1
@@ -23,14 +27,16 @@ _ip = C.POINTER(C.c_int)
 
 
 def build(verbose: bool = False) -> str:
-    """Compile liboracle.so with g++ (plain FP64, no fused multiply-add contraction)."""
+    """Compile liboracle.so and liboracle_wide.so with g++ (plain FP64, no
+    fused multiply-add contraction)."""
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-o", LIB_PATH + ".tmp"] + srcs
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    for path, extra in ((LIB_PATH, []), (WIDE_LIB_PATH, [f"-DORC_MAXS={WIDE_MAXS}"])):
+        cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"] + extra + \
+              ["-o", path + ".tmp"] + srcs
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(path + ".tmp", path)
     return LIB_PATH
 
 
@@ -43,17 +49,18 @@ class OrcMechanism(C.Structure):
                 ("mu_ref", C.c_double), ("T_ref", C.c_double), ("mu_exp", C.c_double)]
 
 
-_lib = None
+_lib = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(wide: bool = False):
+    path = WIDE_LIB_PATH if wide else LIB_PATH
+    if path not in _lib:
+        if not os.path.exists(path):
             build()
-        _lib = C.CDLL(LIB_PATH)
-        _lib.orc_last_error.restype = C.c_char_p
-    return _lib
+        L = C.CDLL(path)
+        L.orc_last_error.restype = C.c_char_p
+        _lib[path] = L
+    return _lib[path]
 
 
 def _d(a):
@@ -69,8 +76,9 @@ def _i(a):
 class Oracle:
     """One oracle context: grid + mechanism + free stream + state."""
 
-    def __init__(self, threads: int = 0):
-        self.L = lib()
+    def __init__(self, threads: int = 0, wide: bool = False):
+        """wide: the build with room for up to 256 species (needed above 32)."""
+        self.L = lib(wide)
         self.ctx = C.c_void_p()
         self._check(self.L.orc_create(C.byref(self.ctx)))
         if threads:
@@ -283,7 +291,7 @@ class Oracle:
 
 def setup(cfg_or_grid, mech, fs, q0=None, T_wall=300.0, bc_mode=0, threads=0):
     """Convenience: oracle with grid (x, y), mechanism and free stream (rho_s, u, v, T, Tv)."""
-    o = Oracle(threads)
+    o = Oracle(threads, wide=mech.ns > 32)
     x, y = cfg_or_grid
     o.set_grid(x, y, T_wall, bc_mode)
     o.set_mechanism(mech)

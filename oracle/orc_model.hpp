@@ -27,7 +27,12 @@ using cplx = std::complex<double>;
 inline double re(double x) { return x; }
 inline double re(const cplx &x) { return x.real(); }
 
-constexpr int MAXS = 32;           // species limit
+// species limit of the fixed-size per-cell arrays: 32 in the default build,
+// larger in the wide build (-DORC_MAXS=256) used for the species-count study
+#ifndef ORC_MAXS
+#define ORC_MAXS 32
+#endif
+constexpr int MAXS = ORC_MAXS;
 constexpr int MAXV = MAXS + 4;     // stored variables limit
 constexpr double Ru = 8.314462618;   // J/(mol K)
 constexpr double kB = 1.380649e-23;  // J/K

@@ -33,7 +33,9 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_set_sweep", "csi_mlp_sizes", "csi_mlp_prepare", "csi_mlp_forward", "csi_mlp_grad",
             "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate", "csi_mlp_forward_noalloc",
             "csi_set_species_jacobian", "csi_set_physical_time", "csi_advance_time",
-            "csi_set_time_levels", "csi_set_offdiag", "csi_mlp_train_epoch"]
+            "csi_set_time_levels", "csi_set_offdiag", "csi_mlp_train_epoch", "csi_set_species_generic",
+            "csi_block_inverse", "csi_block_inverse_work"]
+WIDE_MAX_SPECIES = 4096
 PHASES = ["prim", "faces", "cell", "block", "norms", "sweep_fwd", "sweep_bwd", "update"]
 
 
@@ -102,7 +104,9 @@ class Solver:
     """One library context on cuda:`device` with its workspace tensor."""
 
     def __init__(self, grid, mech, freestream, T_wall: float = 300.0, bc_mode: int = 0, device: int = 0,
-                 stream=None):
+                 stream=None, generic: bool = False):
+        """generic: the species-generic kernels for any species count (they
+        are taken anyway above 32 species)."""
         import torch
         self.torch = torch
         self.L = load()
@@ -121,6 +125,7 @@ class Solver:
         xa, xp = _d(x)
         ya, yp = _d(y)
         self._check(self.L.csi_set_grid(self.ctx, self.ni, self.nj, xp, yp, C.c_double(T_wall), bc_mode))
+        self._check(self.L.csi_set_species_generic(self.ctx, 1 if generic else 0))
         self.set_mechanism(mech)
         self.set_freestream(*freestream)
         nbytes = C.c_size_t(0)
@@ -321,6 +326,37 @@ class Solver:
 
     def synchronize(self):
         self.torch.cuda.synchronize(self.dev)
+
+
+def block_inverse(a, device=0, stream=None):
+    """In-place inverse of the dense FP64 matrices a[..., n, n] (a contiguous
+    cuda tensor) by the library's blocked Gauss-Jordan kernels; returns a."""
+    import torch
+    L = load()
+    if a.dtype != torch.float64 or not a.is_cuda or not a.is_contiguous() or a.dim() < 2 or a.shape[-1] != a.shape[-2]:
+        raise ValueError("block_inverse: contiguous cuda float64 tensor of square matrices expected")
+    n = a.shape[-1]
+    count = a.numel() // (n * n) if n else 0
+    dev = torch.device("cuda", device)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    ctx = C.c_void_p()
+    rc = L.csi_create(C.byref(ctx), device, C.c_void_p(st.cuda_stream))
+    if rc:
+        raise CsiError(rc, "csi_create")
+    try:
+        wb = C.c_size_t(0)
+        rc = L.csi_block_inverse_work(n, count, C.byref(wb))
+        if rc:
+            raise CsiError(rc, "csi_block_inverse_work")
+        work = torch.empty(wb.value, dtype=torch.uint8, device=dev)
+        sing = C.c_int(-1)
+        rc = L.csi_block_inverse(ctx, n, count, C.c_void_p(a.data_ptr()), C.c_void_p(work.data_ptr()),
+                                 C.c_size_t(wb.value), C.byref(sing))
+        if rc:
+            raise CsiError(rc, L.csi_last_error(ctx).decode())
+    finally:
+        L.csi_destroy(ctx)
+    return a
 
 
 class Mlp:

@@ -2,6 +2,7 @@
 // tables, workspace layout inside the caller's device buffer, and the launch
 // sequence of each call.  No device memory is allocated here.
 #include <climits>
+#include <cstddef>
 #include <mutex>
 #include <cmath>
 #include <cstring>
@@ -92,7 +93,11 @@ struct csi_ctx {
   Mech mech;
   int ns = 0, nt = 1;
   IRunner *run = nullptr;
-  double qfs[MAXS + 4];
+  std::vector<double> qfs;
+  // species-generic kernels (one temperature, no reactions): chosen above 32
+  // species, or for every count after csi_set_species_generic(ctx, 1)
+  bool wide = false;
+  bool want_wide = false;
   bool has_grid = false, has_mech = false, has_fs = false, bound = false, has_state = false, has_res = false;
   int last_mode = -1, last_prec = -1;
   bool has_dq = false;
@@ -181,11 +186,21 @@ Layout layout(const csi_ctx *c, int nprim) {
   const size_t ndinv = std::max<size_t>(size_t(c->nb()) * c->nb(), 6 + size_t(c->ns) * c->ns);
   const size_t nblk = (N + 255) / 256;
   const size_t A = N;
-  // group-schedule records, per part
-  GroupCap g0 = group_cap(c->ni, c->nj, PART_COUPLED, c->ns, c->nt);
-  g0.merge(group_cap(c->ni, c->nj, PART_FLOW, c->ns, c->nt));
-  const GroupCap g1 = group_cap(c->ni, c->nj, PART_SPECIES, c->ns, c->nt);
-  const MlpDims sd = mlp_dims(c->ns + 3, c->ns * c->ns);
+  // group-schedule records, per part (none on the species-generic path,
+  // which has neither the group schedule nor the surrogate)
+  GroupCap g0, g1;
+  MlpDims sd{};
+  size_t wtab = 0, gj_perm = 0, gj_xk = 0;
+  if (!c->wide) {
+    g0 = group_cap(c->ni, c->nj, PART_COUPLED, c->ns, c->nt);
+    g0.merge(group_cap(c->ni, c->nj, PART_FLOW, c->ns, c->nt));
+    g1 = group_cap(c->ni, c->nj, PART_SPECIES, c->ns, c->nt);
+    sd = mlp_dims(c->ns + 3, c->ns * c->ns);
+  } else {
+    (void)c->run->host_table(&wtab);
+    gj_perm = N * size_t(c->nb()) * 4;
+    gj_xk = N * size_t(WGJ_SCRATCH_ROWS) * c->nb() * 8;
+  }
   size_t sizes[] = {
       sizeof(Mech),                       // 0 mech
       N * 8, N * 8, N * 8, NN * 8, NN * 8, // 1-5 V xc yc xn yn
@@ -204,14 +219,15 @@ Layout layout(const csi_ctx *c, int nprim) {
       FL_N * 4,                                       // 31 flags
       g0.S, g0.x, g0.bnd, g0.bnd, 8,                  // 32-36 group part 0: record staging, dQ, pushes (fwd, bwd), tickets
       g1.S, g1.x, g1.bnd, g1.bnd, 8,                  // 37-41 group part 1
-      size_t(c->ns) * c->ns * N * 4,                  // 42 surrogate J_C
+      c->wide ? 0 : size_t(c->ns) * c->ns * N * 4,    // 42 surrogate J_C
       size_t(sd.nslots) * 16,                         // 43 surrogate packed operands
       size_t(sd.np) * 4,                              // 44 surrogate FP32 parameters
       size_t(2 * sd.n_in + 1) * 8,                    // 45 surrogate scales
       size_t(4) * c->ni * TR_N * 8,                   // 46 sweep trace
-      size_t(c->ns >= BLOCK_NS_MIN ? hb_fields(c->ns, nv) : 2) * N * 8,  // 47 cell kernel -> block kernel hand-off
+      size_t(c->ns >= BLOCK_NS_MIN && !c->wide ? hb_fields(c->ns, nv) : 2) * N * 8,  // 47 cell kernel -> block kernel hand-off
       size_t(nv) * N * 8,                             // 48 state at the start of csi_step (surrogate divergence fallback)
       size_t(nv) * N * 8, size_t(nv) * N * 8,         // 49-50 physical-time levels Q^n, Q^{n-1}
+      wtab, gj_perm, gj_xk,                           // 51-53 species-generic table and Gauss-Jordan scratch
   };
   for (size_t s : sizes) { L.off[k++] = o; o += al(s); }
   L.total = o;
@@ -317,18 +333,31 @@ int csi_set_grid(csi_ctx *c, int ni, int nj, const double *xn, const double *yn,
 
 int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
   if (!c || !mm) return CSI_ERR_ARG;
-  if (mm->ns < 2 || mm->ns > MAXS || mm->nr < 0 || mm->nr > MAXR) return c->fail(CSI_ERR_ARG, "set_mechanism: sizes");
-  IRunner *r = make_runner(mm->ns, mm->two_temp ? 2 : 1);
-  if (!r)
-    return c->fail(CSI_ERR_UNSUPPORTED, "no kernels compiled for ns = " + std::to_string(mm->ns) +
-                                            (mm->two_temp ? " with two temperatures" : " with one temperature"));
+  if (mm->ns < 2 || mm->ns > CSI_WIDE_MAX_SPECIES || mm->nr < 0 || mm->nr > MAXR)
+    return c->fail(CSI_ERR_ARG, "set_mechanism: sizes");
+  const bool wide = c->want_wide || mm->ns > MAXS;
   std::string err;
-  if (!build_mech(mm, c->mech, err)) { delete r; return c->fail(CSI_ERR_ARG, "set_mechanism: " + err); }
+  IRunner *r = nullptr;
+  if (wide) {
+    if (mm->nr != 0 || mm->two_temp)
+      return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels (ns = " + std::to_string(mm->ns) +
+                                              ") take one temperature and no reactions");
+    r = make_wide_runner(mm, err);
+    if (!r) return c->fail(CSI_ERR_ARG, "set_mechanism: " + err);
+    std::memset(&c->mech, 0, sizeof(Mech));  // the generic runner reads its own table
+  } else {
+    r = make_runner(mm->ns, mm->two_temp ? 2 : 1);
+    if (!r)
+      return c->fail(CSI_ERR_UNSUPPORTED, "no kernels compiled for ns = " + std::to_string(mm->ns) +
+                                              (mm->two_temp ? " with two temperatures" : " with one temperature"));
+    if (!build_mech(mm, c->mech, err)) { delete r; return c->fail(CSI_ERR_ARG, "set_mechanism: " + err); }
+  }
   delete c->run;
   c->run = r;
+  c->wide = wide;
   c->ns = mm->ns;
   c->nt = mm->two_temp ? 2 : 1;
-  c->group_c = 1;  // persistent group kernels
+  c->group_c = wide ? 0 : 1;  // persistent group kernels (per-hyperplane launches on the generic path)
   c->has_mech = true;
   // the species block with the temperature following the composition in one
   // temperature; at fixed T, Tv in two (the default readings)
@@ -344,10 +373,11 @@ int csi_set_freestream(csi_ctx *c, const double *rho_s, double u, double v, doub
   if (!c || !rho_s) return CSI_ERR_ARG;
   if (!c->has_mech) return c->fail(CSI_ERR_STATE, "set_freestream before set_mechanism");
   if (!(T > 0.0) || (c->nt == 2 && !(Tv > 0.0))) return c->fail(CSI_ERR_ARG, "free-stream temperature");
-  (void)c->run->q_from_prim_host(c->mech, rho_s, u, v, T, Tv, c->qfs);
+  c->qfs.assign(c->nv(), 0.0);
+  (void)c->run->q_from_prim_host(c->mech, rho_s, u, v, T, Tv, c->qfs.data());
   c->has_fs = true;
   if (c->bound) {
-    int rc = hip_check(c, hipMemcpyAsync(c->w.qfs, c->qfs, c->nv() * 8, hipMemcpyHostToDevice, c->stream), "qfs");
+    int rc = hip_check(c, hipMemcpyAsync(c->w.qfs, c->qfs.data(), c->nv() * 8, hipMemcpyHostToDevice, c->stream), "qfs");
     if (rc) return rc;
     return hip_check(c, hipStreamSynchronize(c->stream), "sync");
   }
@@ -399,6 +429,28 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.qbak = D(48);
   w.qn = D(49);
   w.qnm1 = D(50);
+  w.wtab = D(51);
+  w.gj_perm = reinterpret_cast<int *>(b + L.off[52]);
+  w.gj_xk = D(53);
+  {
+    // the compiled table as the streaming kernels read it (views into the
+    // device Mech record)
+    const char *mb = reinterpret_cast<const char *>(w.mech);
+    WMech &v = w.mview;
+    v.ns = c->ns;
+    v.R = reinterpret_cast<const double *>(mb + offsetof(Mech, R));
+    v.cvtr = reinterpret_cast<const double *>(mb + offsetof(Mech, cvtr));
+    v.thv = reinterpret_cast<const double *>(mb + offsetof(Mech, thv));
+    v.hf = reinterpret_cast<const double *>(mb + offsetof(Mech, hf));
+    v.ck = reinterpret_cast<const double *>(mb + offsetof(Mech, ck));
+    v.iSc = reinterpret_cast<const double *>(mb + offsetof(Mech, iSc));
+    v.kind = reinterpret_cast<const int *>(mb + offsetof(Mech, kind));
+    v.mu_ref = c->mech.mu_ref;
+    v.T_ref = c->mech.T_ref;
+    v.mu_exp = c->mech.mu_exp;
+    v.iscmax = 0.0;
+    for (int s_ = 0; s_ < c->ns && !c->wide; ++s_) v.iscmax = std::fmax(v.iscmax, c->mech.iSc[s_]);
+  }
   w.pt_a = c->pt_a;
   w.pt_b = c->pt_b;
   w.fdiff = c->fdiff;
@@ -428,7 +480,12 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   if (e == hipSuccess) e = up(w.fj_nx, c->fj_nx);
   if (e == hipSuccess) e = up(w.fj_ny, c->fj_ny);
   if (e == hipSuccess) e = up(w.fj_S, c->fj_S);
-  if (e == hipSuccess) e = hipMemcpyAsync(w.qfs, c->qfs, c->nv() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w.qfs, c->qfs.data(), c->nv() * 8, hipMemcpyHostToDevice, st);
+  {
+    size_t tb = 0;
+    const void *tab = c->run->host_table(&tb);
+    if (tab && e == hipSuccess) e = hipMemcpyAsync(w.wtab, tab, tb, hipMemcpyHostToDevice, st);
+  }
   if (e == hipSuccess) e = hipMemsetAsync(w.qw, 0, size_t(c->ni) * 8, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   int rc = hip_check(c, e, "bind_workspace");
@@ -466,6 +523,8 @@ int csi_set_physical_time(csi_ctx *c, double dt, double theta) {
   if (!c) return CSI_ERR_ARG;
   if (!(dt >= 0.0) || !(theta >= 0.0) || !std::isfinite(dt) || !std::isfinite(theta))
     return c->fail(CSI_ERR_ARG, "set_physical_time: dt and theta must be finite and >= 0");
+  if (c->wide && dt > 0.0)
+    return c->fail(CSI_ERR_UNSUPPORTED, "physical time on the species-generic kernels: steady only");
   c->pt_a = dt > 0.0 ? (1.0 + theta) / dt : 0.0;
   c->pt_b = dt > 0.0 ? theta / dt : 0.0;
   c->w.pt_a = c->pt_a;
@@ -547,6 +606,8 @@ int csi_implicit_op(csi_ctx *c, int mode, int precision, int jac) {
   if (!ready(c) || !c->has_res) return c->fail(CSI_ERR_STATE, "implicit_op before residual");
   if (c->fdiff && precision != CSI_FP64)
     return c->fail(CSI_ERR_UNSUPPORTED, "flux-difference off-diagonal operator: FP64 sweeps only");
+  if (c->wide && precision != CSI_FP64)
+    return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels sweep in FP64 only");
   hipError_t e = hipSuccess;
   if (jac == CSI_JAC_SURROGATE) e = c->run->surrogate(c->g, c->w, c->stream, false);
   if (e == hipSuccess) e = c->run->cell(c->g, c->w, c->stream, 0.0, mode, precision, (jac == CSI_JAC_SURROGATE ? 6 : 2) | c->jc_flag(), false);
@@ -602,6 +663,8 @@ int csi_step(csi_ctx *c, const csi_step_params *p, csi_step_stats *s) {
   if (sur && !c->has_sur) return c->fail(CSI_ERR_STATE, "step: no surrogate installed");
   if (c->fdiff && p->precision != CSI_FP64)
     return c->fail(CSI_ERR_UNSUPPORTED, "flux-difference off-diagonal operator: FP64 sweeps only");
+  if (c->wide && p->precision != CSI_FP64)
+    return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels sweep in FP64 only");
   int rc = reset_flags(c);
   if (rc) return rc;
   if (sur && !c->side) {
@@ -774,10 +837,10 @@ int csi_prim_to_cons(csi_ctx *c, int n, const double *rho_s, const double *u, co
   if (!c || n < 0 || !rho_s || !u || !v || !T || !q) return CSI_ERR_ARG;
   if (!c->has_mech) return c->fail(CSI_ERR_STATE, "prim_to_cons before set_mechanism");
   const int ns = c->ns, nv = c->nv();
-  double rs[MAXS], qq[MAXS + 4];
+  std::vector<double> rs(ns), qq(nv);
   for (int p = 0; p < n; ++p) {
     for (int s = 0; s < ns; ++s) rs[s] = rho_s[size_t(s) * n + p];
-    (void)c->run->q_from_prim_host(c->mech, rs, u[p], v[p], T[p], Tv ? Tv[p] : T[p], qq);
+    (void)c->run->q_from_prim_host(c->mech, rs.data(), u[p], v[p], T[p], Tv ? Tv[p] : T[p], qq.data());
     for (int k = 0; k < nv; ++k) q[size_t(k) * n + p] = qq[k];
   }
   return CSI_OK;
@@ -786,6 +849,8 @@ int csi_prim_to_cons(csi_ctx *c, int n, const double *rho_s, const double *u, co
 int csi_set_sweep(csi_ctx *c, int schedule) {
   if (!c) return CSI_ERR_ARG;
   if (schedule != 0 && schedule != 1) return c->fail(CSI_ERR_ARG, "sweep schedule must be 0 or 1");
+  if (c->wide && schedule != 0)
+    return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels sweep with per-hyperplane launches only");
   c->group_c = schedule;
   c->w.group_c = schedule;
   c->last_mode = -1;  // the records of the last operator are in the old layout
@@ -797,10 +862,66 @@ int csi_set_sweep(csi_ctx *c, int schedule) {
 int csi_set_offdiag(csi_ctx *c, int op) {
   if (!c) return CSI_ERR_ARG;
   if (op != 0 && op != 1) return c->fail(CSI_ERR_ARG, "off-diagonal operator must be 0 or 1");
+  if (c->wide && op != 0)
+    return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels apply the linear Jacobian-vector product only");
   c->fdiff = op;
   c->w.fdiff = op;
   if (op == 1) return csi_set_sweep(c, 0);  // flux differences run in the per-hyperplane sweeps
   c->has_dq = false;
+  return CSI_OK;
+}
+
+int csi_set_species_generic(csi_ctx *c, int on) {
+  if (!c) return CSI_ERR_ARG;
+  if (on != 0 && on != 1) return c->fail(CSI_ERR_ARG, "set_species_generic: on must be 0 or 1");
+  c->want_wide = on != 0;
+  return CSI_OK;
+}
+
+namespace {
+// scratch of csi_block_inverse: row interchanges, pivot rows, singular flag
+void block_inverse_layout(int n, int count, size_t off[3], size_t *total) {
+  off[0] = 0;
+  off[1] = al(size_t(count) * n * 4);
+  off[2] = off[1] + al(size_t(count) * WGJ_SCRATCH_ROWS * n * 8);
+  *total = off[2] + 256;
+}
+}  // namespace
+
+int csi_block_inverse_work(int n, int count, size_t *bytes) {
+  if (!bytes || n < 1 || n > CSI_WIDE_MAX_SPECIES + 3 || count < 0) return CSI_ERR_ARG;
+  size_t off[3];
+  block_inverse_layout(n, count, off, bytes);
+  return CSI_OK;
+}
+
+int csi_block_inverse(csi_ctx *c, int n, int count, double *a, void *work, size_t work_bytes, int *singular) {
+  if (!c) return CSI_ERR_ARG;
+  if (n < 1 || n > CSI_WIDE_MAX_SPECIES + 3 || count < 0 || (count > 0 && !a))
+    return c->fail(CSI_ERR_ARG, "block_inverse: bad arguments");
+  size_t off[3], need = 0;
+  block_inverse_layout(n, count, off, &need);
+  if (!work || reinterpret_cast<uintptr_t>(work) % 256 || work_bytes < need)
+    return c->fail(CSI_ERR_ARG, "block_inverse: work buffer missing, not 256-byte aligned or too small");
+  if (singular) *singular = -1;
+  if (count == 0) return CSI_OK;
+  char *w = static_cast<char *>(work);
+  int *perm = reinterpret_cast<int *>(w + off[0]);
+  double *xk = reinterpret_cast<double *>(w + off[1]);
+  int *sing = reinterpret_cast<int *>(w + off[2]);
+  const int none = INT_MAX;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipMemcpyAsync(sing, &none, 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = wide_invert(a, n, count, perm, xk, sing, nullptr, c->stream);
+  int hs = INT_MAX;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hs, sing, 4, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  int rc = hip_check(c, e, "block_inverse");
+  if (rc) return rc;
+  if (hs != INT_MAX) {
+    if (singular) *singular = hs;
+    return c->fail(CSI_ERR_SINGULAR, "block_inverse: singular matrix " + std::to_string(hs));
+  }
   return CSI_OK;
 }
 
@@ -836,6 +957,7 @@ namespace {
 // schedule or un-permutes the step-blocked group records.
 int get_records(csi_ctx *c, const std::string &n, double *out, size_t count) {
   const size_t N = c->N;
+  if (c->wide && n == "Dinv") return c->fail(CSI_ERR_UNSUPPORTED, "Dinv: not kept in this layout by the species-generic kernels");
   const bool coupled = c->last_mode == CSI_COUPLED;
   const int nsol = coupled ? c->nb() : c->nsplit();
   const int nf = c->nf(), ns = c->ns, nb = c->nb();
@@ -910,6 +1032,7 @@ int get_records(csi_ctx *c, const std::string &n, double *out, size_t count) {
 // full-size runs are checked at sampled cells without copying whole fields.
 int get_cells(csi_ctx *c, const std::string &n, const long long *cells, int nc, double *out) {
   const size_t N = c->N;
+  if (c->wide && n == "Dinv") return c->fail(CSI_ERR_UNSUPPORTED, "Dinv: not kept in this layout by the species-generic kernels");
   auto elem = [&](const void *base, size_t idx, size_t esz, double &v) -> int {
     if (esz == 8) return hip_check(c, hipMemcpy(&v, static_cast<const char *>(base) + idx * 8, 8, hipMemcpyDeviceToHost), "get");
     float f = 0.f;
@@ -1251,6 +1374,7 @@ int csi_sample_jacobians(csi_ctx *c, int max_samples, float *x_raw, float *jc, i
   if (!c) return CSI_ERR_ARG;
   if (max_samples < 1 || !x_raw || !jc) return c->fail(CSI_ERR_ARG, "sample_jacobians: arguments");
   if (!ready(c)) return c->fail(CSI_ERR_STATE, "sample_jacobians: workspace/state not set");
+  if (c->wide) return c->fail(CSI_ERR_UNSUPPORTED, "sample_jacobians: no reactions on the species-generic kernels");
   const int n = max_samples < c->N ? max_samples : c->N;
   int rc = hip_check(c, c->run->sample(c->g, c->w, c->stream, n, x_raw, jc, c->jc_flag()), "sample launch");
   if (rc) return rc;
@@ -1266,6 +1390,7 @@ int csi_set_surrogate(csi_ctx *c, const float *params, const double *scales, int
                       int stall_window) {
   if (!c) return CSI_ERR_ARG;
   if (!c->bound) return c->fail(CSI_ERR_STATE, "set_surrogate before bind_workspace");
+  if (c->wide) return c->fail(CSI_ERR_UNSUPPORTED, "set_surrogate: not on the species-generic kernels");
   if (!params || !scales || n_in != c->ns + 3 || n_out != c->ns * c->ns || !(stall_ratio > 0.0) || stall_window < 1)
     return c->fail(CSI_ERR_ARG, "set_surrogate: expects n_in = ns + 3, n_out = ns^2, ratio > 0, window >= 1");
   for (int k = 0; k < 2 * n_in + 1; ++k)

@@ -27,6 +27,23 @@ template <int NS> struct PF {
 // face radius fields
 enum { R_LAM = 0, R_UABS, R_LVF, R_LVC, R_LVK, R_N };
 
+// species table read by the streaming (run-time species count) kernels of
+// one temperature: device arrays of length ns (the species-generic path's
+// own table, or views into a Mech record)
+struct WMech {
+  int ns;
+  const double *R, *cvtr, *thv, *hf, *ck, *iSc;
+  const int *kind;
+  double mu_ref, T_ref, mu_exp, iscmax;
+};
+
+// primitive record fields with a run-time species count (same order as PF)
+struct WF {
+  int Y, HS, EVS, PR, N;
+  __host__ __device__ explicit WF(int ns) : Y(F_Y0), HS(F_Y0 + ns), EVS(F_Y0 + 2 * ns), PR(F_Y0 + 3 * ns),
+                                            N(F_Y0 + 4 * ns) {}
+};
+
 __device__ __forceinline__ int padc(const Geo &g, int i, int j) { return (j + 1) * (g.ni + 2) + (i + 1); }
 
 // --------------------------------------------------------------- primitives

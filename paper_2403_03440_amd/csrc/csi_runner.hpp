@@ -2,6 +2,9 @@
 // count and the temperature model; instantiated per species count in
 // csi_inst.hip and dispatched through the IRunner interface.
 #pragma once
+#include <string>
+
+#include "../../include/csi.h"
 #include "csi_block.hpp"
 #include "csi_group.hpp"
 #include "csi_surrogate.hpp"
@@ -26,6 +29,13 @@ struct WS {
   int group_c;               // 0: one launch per hyperplane; 1: persistent group kernels
   long spin_limit;
   SurArgs sur;               // surrogate network (packed operands, biases, scales) and its J_C buffer
+  // species-generic path: species table, and the Gauss-Jordan scratch of the
+  // coupled blocks (row interchanges [N][nb], pivot rows [N][64][nb])
+  double *wtab;
+  int *gj_perm;
+  double *gj_xk;
+  // the species table as the streaming kernels read it (one temperature)
+  WMech mview;
 };
 // flags[]: ints, with one 64-bit counter at int offset FL_DDFAIL
 enum {
@@ -58,9 +68,34 @@ class IRunner {
                             bool stoppable) = 0;
   virtual hipError_t q_from_prim_host(const Mech &m, const double *rs, double u, double v, double T, double Tv,
                                       double *q) = 0;
+  // species table the runner reads from the workspace (species-generic
+  // runner; null for the compiled ones, which read the Mech record)
+  virtual const void *host_table(size_t *bytes) const {
+    *bytes = 0;
+    return nullptr;
+  }
 };
 
 IRunner *make_runner(int ns, int nt);
+// Streaming primitive and face kernels (one thread per padded cell / face,
+// loops over the species instead of per-thread species arrays; one
+// temperature).  The compiled runners take them from STREAM_NS_MIN species
+// on, where the register-resident versions run at one wave per SIMD.
+constexpr int STREAM_NS_MIN = 16;
+hipError_t launch_stream_prim(const Geo &g, const WMech &m, const double *Q, const double *qfs, double *prim,
+                              int *bad, const int *done, int guess, hipStream_t st);
+hipError_t launch_stream_faces(const Geo &g, const WMech &m, const double *prim, double *Fi, double *Ri, double *Fj,
+                               double *Rj, double *qw, const int *done, hipStream_t st);
+// pivot rows kept per cell by the blocked Gauss-Jordan inversion (its panel width)
+constexpr int WGJ_SCRATCH_ROWS = 64;
+// species-generic runner (one temperature, no reactions); null with err set
+// on a bad species record
+IRunner *make_wide_runner(const csi_mechanism *mm, std::string &err);
+// in-place blocked Gauss-Jordan inverse of `count` row-major n x n FP64
+// matrices at W; perm [count][n] and XK [count][64][n] of scratch; sing
+// receives (atomic minimum) the index of a singular matrix
+hipError_t wide_invert(double *W, int n, int count, int *perm, double *XK, int *sing, const int *done,
+                       hipStream_t st);
 
 inline int nblocks(long n, int b = 256) { return int((n + b - 1) / b); }
 
@@ -76,6 +111,9 @@ template <int NS, int NT> class Runner : public IRunner {
   int nprim() const override { return PF<NS>::N; }
 
   hipError_t prim(const Geo &g, const WS &w, hipStream_t st, bool stoppable, bool guess) override {
+    if constexpr (NT == 1 && NS >= STREAM_NS_MIN)
+      return launch_stream_prim(g, w.mview, w.Q, w.qfs, w.prim, w.flags + FL_BAD,
+                                stoppable ? w.flags + FL_DONE : nullptr, guess ? 1 : 0, st);
     hipLaunchKernelGGL((k_prim<NS, NT>), dim3(nblocks(g.NP)), dim3(256), 0, st, g, w.mech, w.Q, w.qfs, w.prim,
                        w.flags + FL_BAD, stoppable ? w.flags + FL_DONE : nullptr, guess ? 1 : 0);
     return hipGetLastError();
@@ -83,6 +121,8 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) override {
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    if constexpr (NT == 1 && NS >= STREAM_NS_MIN)
+      return launch_stream_faces(g, w.mview, w.prim, w.Fi, w.Ri, w.Fj, w.Rj, w.qw, done, st);
     hipLaunchKernelGGL((k_face_i<NS, NT>), dim3(nblocks(long(g.ni + 1) * g.nj)), dim3(256), 0, st, g, w.mech, w.prim,
                        w.Fi, w.Ri, done);
     hipLaunchKernelGGL((k_face_j<NS, NT>), dim3(nblocks(long(g.ni) * (g.nj + 1))), dim3(256), 0, st, g, w.mech,

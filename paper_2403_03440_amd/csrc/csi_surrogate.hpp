@@ -87,18 +87,30 @@ __global__ void __launch_bounds__(256) k_surrogate(Geo g, const double *__restri
   float h1[4][4], h2[4][4];
   u16x8 B2[2];
   mlp_hidden<KS1>(d, a.P, a.p, xin, h1, h2, B2);
-  const double itau = 1.0 / a.scales[2 * NIN];
+  // J is stored in FP32 and y comes from FP32 accumulation: sinh in FP32
+  // (a few ulp) keeps the stored value within a few FP32 roundings of the
+  // double-precision expression, at a fraction of its cost
+  const float itau = float(1.0 / a.scales[2 * NIN]);
   // layout of J: [ns * ns][N] where the cell kernel reads it (one thread per
   // cell, ns < 5); cell-major [N][ns * ns] where the block kernel does (each
   // lane reads one contiguous row of its cell's block)
+  constexpr int NN = NS * NS;
   constexpr bool CELL_MAJOR = NS >= BLOCK_NS_MIN;
   for (int t = 0; t < d.nt3; ++t) {
-    f32x4 y = mlp_out_tile(d, a.P, a.p, B2, t);
+    const f32x4 y = mlp_out_tile(d, a.P, a.p, B2, t);
+    const int o0 = 16 * t + 4 * gq;
+    f32x4 v;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = 16 * t + 4 * gq + r;
-      const size_t at = CELL_MAJOR ? size_t(p) * (NS * NS) + o : size_t(o) * g.N + p;
-      if (valid && o < NS * NS) a.J[at] = float(sinh(double(y[r])) * itau);
+    for (int r = 0; r < 4; ++r) v[r] = sinhf(y[r]) * itau;
+    if (!valid) continue;
+    if constexpr (CELL_MAJOR && NN % 4 == 0) {
+      // a lane's four outputs are consecutive entries of its cell's block and
+      // the block starts on a 16-byte boundary: one 16-byte store
+      if (o0 < NN) *reinterpret_cast<f32x4 *>(a.J + size_t(p) * NN + o0) = v;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (o0 + r < NN) a.J[CELL_MAJOR ? size_t(p) * NN + o0 + r : size_t(o0 + r) * g.N + p] = v[r];
     }
   }
 }

@@ -85,6 +85,31 @@ class Mechanism:
             third=np.zeros(0, np.int32), nu_f=z, nu_b=z, eff=np.zeros((0, self.ns)), reactions=[])
 
 
+def species_copies(mech: Mechanism, ns: int) -> Mechanism:
+    """A non-reacting mixture of ns species in which species k is an identical
+    copy of species k mod mech.ns (same molar mass, modes and transport).
+    Giving the copies of a species fractions of its partial density that sum
+    to it leaves every mixture property unchanged, so the flow unknowns match
+    the base mixture's at any species count."""
+    if mech.nr:
+        raise ValueError("species_copies: the base mechanism must have no reactions")
+    idx = np.arange(ns) % mech.ns
+    z = np.zeros((0, ns), dtype=np.int32)
+    return dataclasses.replace(
+        mech, names=[f"{mech.names[k]}#{i}" for i, k in enumerate(idx)], M=mech.M[idx], kind=mech.kind[idx],
+        theta_v=mech.theta_v[idx], theta_r=mech.theta_r[idx], sigma=mech.sigma[idx], g_el=mech.g_el[idx],
+        h_form=mech.h_form[idx], sc=mech.sc[idx], lt_a=mech.lt_a[idx], lt_b=mech.lt_b[idx], nu_f=z, nu_b=z,
+        eff=np.zeros((0, ns)), reactions=[])
+
+
+def split_among_copies(rho_s: np.ndarray, base_ns: int, ns: int) -> np.ndarray:
+    """Partial densities of the species_copies mixture: each base species'
+    density shared equally among its copies (rho_s: [base_ns, n])."""
+    idx = np.arange(ns) % base_ns
+    counts = np.bincount(idx, minlength=base_ns).astype(np.float64)
+    return np.ascontiguousarray(rho_s[idx] / counts[idx][:, None])
+
+
 # --------------------------------------------------------------- species
 def _millikan_white(M_kg: float, theta_v: float):
     """Millikan-White correlation constants a_s, b_s with the species' own reduced mass (amu)."""
@@ -290,7 +315,7 @@ def synthetic(ns: int = 20, nr: int = 60, seed: int = 3442) -> Mechanism:
     names, M, kind, tv, tr, sig, g, hf, sc, a, bb = _species_table(rows)
     cidx = {c: k for k, c in enumerate(comps)}
     cand = []
-    for k, c in enumerate(comps):  # dissociations A -> B + C
+    for k, c in enumerate(comps if nr > 0 else []):  # dissociations A -> B + C
         if sum(c) < 2:
             continue
         for k2, c2 in enumerate(comps):
@@ -298,7 +323,7 @@ def synthetic(ns: int = 20, nr: int = 60, seed: int = 3442) -> Mechanism:
             if min(rest) < 0 or sum(rest) == 0 or rest not in cidx or cidx[rest] < k2:
                 continue
             cand.append(("d", k, k2, cidx[rest]))
-    for k, c in enumerate(comps):  # exchanges X + Y -> X' + Y' moving one atom
+    for k, c in enumerate(comps if nr > 0 else []):  # exchanges X + Y -> X' + Y' moving one atom
         for e in range(3):
             if c[e] == 0 or sum(c) < 2:
                 continue
