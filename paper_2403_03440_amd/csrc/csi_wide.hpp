@@ -495,8 +495,11 @@ __global__ void __launch_bounds__(256) kw_gj_panel(double *__restrict__ W, int n
   __shared__ double bv[4];
   __shared__ int bi[4];
   const int p = blockIdx.x, tid = threadIdx.x;
+  // update mapping: lane jj owns panel column jj, wave rg rows rg, rg + 4, ...
+  const int jj = tid & 63, rg = tid >> 6;
   double *A = W + size_t(p) * n * n;
   const int nbk = min(WGJ_B, n - kb);
+  constexpr int U = 8;  // rows per thread with their loads in flight together
   for (int jk = 0; jk < nbk; ++jk) {
     const int k = kb + jk;
     // pivot: largest |a| in column k among rows k..n-1, lowest row on ties
@@ -536,16 +539,25 @@ __global__ void __launch_bounds__(256) kw_gj_panel(double *__restrict__ W, int n
     for (int r = tid; r < n; r += 256) colk[r] = A[size_t(r) * n + k];
     if (tid < nbk) prow[tid] = A[size_t(k) * n + kb + tid];
     __syncthreads();
-    const double ip = 1.0 / colk[k];
     // the scaled pivot row replaces row k; every other row r takes
     // a_rc - a_rk (a_kc / a_kk), column k becoming -a_rk / a_kk
-    const int tot = n * nbk;
-    for (int e = tid; e < tot; e += 256) {
-      const int r = e / nbk, jj = e - r * nbk;
+    if (jj < nbk) {
+      const double ip = 1.0 / colk[k];
       const double prs = jj == jk ? ip : prow[jj] * ip;
-      double &a = A[size_t(r) * n + kb + jj];
-      if (r == k) a = prs;
-      else a = (jj == jk ? 0.0 : a) - colk[r] * prs;
+      double *col = A + kb + jj;
+      for (int r0 = rg; r0 < n; r0 += 4 * U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = r0 + 4 * u;
+          v[u] = r < n ? col[size_t(r) * n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = r0 + 4 * u;
+          if (r < n) col[size_t(r) * n] = r == k ? prs : (jj == jk ? 0.0 : v[u]) - colk[r] * prs;
+        }
+      }
     }
     __syncthreads();
   }
