@@ -40,6 +40,12 @@ struct BlockOut {
   int *bad;                    // first singular cell
   float *jc_out;               // non-null: write the species block's J_C [n_lim][ns][ns] (FP32) and stop
   long n_lim;                  // cells written with jc_out
+  // one temperature, flags bit 0 (the cell kernel formed the residual in
+  // this pass without the chemical source): R [nv][N] receives the source
+  // -V omega_s of the species rows and the right-hand side's species rows
+  // -R_s are rewritten (hyperplane schedule: b [nsol][N])
+  double *R;
+  void *b;
 };
 
 template <int NS, int NT, int MODE> struct BlockDims {
@@ -411,7 +417,10 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
 #pragma unroll
   for (int u = 0; u < NS; ++u) row[u] = 0.0;
   const bool exact = MODE == 0 || NT == 2 || __ballot(real && !use_sur) != 0ull;
-  if (exact) {
+  // one temperature: the species source of the residual comes from the
+  // reaction records here (the cell kernel left it out)
+  const bool src = NT == 1 && (flags & 1) && !out.jc_out && out.R;
+  if (exact || src) {
     const double lnc0 = log(1.0e5 / (RU * T));
     for (int r0 = 0; r0 < m.nr; r0 += G) {
       if (live && r0 + k < m.nr) reaction_record<NS, NT>(m, r0 + k, T, Tv, lnT, lnTv, lnc0, X, GH, scr + k * RW);
@@ -425,14 +434,33 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
         const double a = av[kk];
         if (kk < nk && a != 0.0) {
           const double *D = scr + kk * RW;
+          if (exact) {
 #pragma unroll
-          for (int u = 0; u < NS; ++u) row[u] += a * D[u];
+            for (int u = 0; u < NS; ++u) row[u] += a * D[u];
+          }
           w_t += a * D[NS];
           dwT += a * D[NS + 1];
           dwTv += a * D[NS + 2];
         }
       }
       wave_sync();
+    }
+  }
+  if (src && real && t >= 0) {
+    const double Rt = out.R[size_t(t) * g.N + p] - Vp * w_t;
+    out.R[size_t(t) * g.N + p] = Rt;
+    // the right-hand side row of species t: split species row t; coupled z
+    // row k (the closing species, lane 0, enters only the total density)
+    const int row_b = MODE == 1 ? t : (k >= NF ? k : -1);
+    if (row_b >= 0) {
+      if (out.group_c > 0) {
+        constexpr RecShape SB = rec_shape(MODE == 1 ? PART_SPECIES : PART_COUPLED, NS, NT, sizeof(RT));
+        RT *Sb = reinterpret_cast<RT *>(out.gS[MODE == 1 ? 1 : 0]);
+        Sb[st_idx(SB, g.N, 1, dw_b(row_b), p)] = RT(-Rt);
+      } else {
+        RT *bb = reinterpret_cast<RT *>(out.b);
+        bb[long(MODE == 1 ? NF + row_b : row_b) * g.N + p] = RT(-Rt);
+      }
     }
   }
   // group sums: Landau-Teller terms (species k), pressure derivatives, the

@@ -550,7 +550,10 @@ struct CellOut {
   double pt_a, pt_b;
 };
 
-template <int NS, int NT, typename RT>
+// SRC_BLOCK (one temperature, ns >= BLOCK_NS_MIN, residual and diagonal in
+// one pass): the chemical source of R is added by the block kernel from its
+// reaction records, so this kernel forms the flux part only
+template <int NS, int NT, typename RT, bool SRC_BLOCK>
 __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
                                               const double *__restrict__ prim, const double *__restrict__ Fi,
                                               const double *__restrict__ Fj, const double *__restrict__ Ri,
@@ -586,8 +589,13 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     constexpr bool BLK = NS >= BLOCK_NS_MIN;
     const bool try_sur = !BLK && do_diag && mode == 1 && (flags & 4) && out.Jsur && *out.surr_off < 0;
     bool have_jac = !BLK && do_diag && !(try_sur && NT == 1);
-    if (have_jac) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
-    else chemistry<NS, NT, false>(m, rs, T, Tv, pp, C);
+    if constexpr (SRC_BLOCK) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) C.w[s] = 0.0;
+    } else {
+      if (have_jac) chemistry<NS, NT, true>(m, rs, T, Tv, pp, C);
+      else chemistry<NS, NT, false>(m, rs, T, Tv, pp, C);
+    }
     double R[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {

@@ -142,12 +142,26 @@ template <int NS, int NT> class Runner : public IRunner {
     CellOut o{w.R, w.dtau, w.part, w.Dinv, w.b, {w.grp[0].S, w.grp[1].S}, w.src, w.flags + FL_SING, w.group_c,
               w.diag, w.sur.J, ddfail_counter(w.flags), w.flags + FL_SURR_OFF, w.qn, w.qnm1, w.pt_a, w.pt_b};
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
-    if (prec == 0)
-      hipLaunchKernelGGL((k_cell<NS, NT, double>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
-                         w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
-    else
-      hipLaunchKernelGGL((k_cell<NS, NT, float>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim, w.Fi,
-                         w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    // one temperature with the block kernel: a pass that forms both the
+    // residual and the blocks takes the species source from the block
+    // kernel's reaction records
+    constexpr bool SB = NT == 1 && NS >= BLOCK_NS_MIN;
+    const bool src_block = SB && (flags & 3) == 3;
+    if (prec == 0) {
+      if (src_block)
+        hipLaunchKernelGGL((k_cell<NS, NT, double, SB>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim,
+                           w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+      else
+        hipLaunchKernelGGL((k_cell<NS, NT, double, false>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q,
+                           w.prim, w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    } else {
+      if (src_block)
+        hipLaunchKernelGGL((k_cell<NS, NT, float, SB>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim,
+                           w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+      else
+        hipLaunchKernelGGL((k_cell<NS, NT, float, false>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q,
+                           w.prim, w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    }
     if (mid) {
       const hipError_t e = hipEventRecord(mid, st);
       if (e != hipSuccess) return e;
@@ -155,7 +169,7 @@ template <int NS, int NT> class Runner : public IRunner {
     if constexpr (NS >= BLOCK_NS_MIN) {
       if (flags & 2) {
         const BlockOut bo{{w.grp[0].S, w.grp[1].S}, w.Dinv, w.group_c, w.diag, w.sur.J, ddfail_counter(w.flags),
-                          w.flags + FL_SURR_OFF, w.flags + FL_SING, nullptr, 0};
+                          w.flags + FL_SURR_OFF, w.flags + FL_SING, nullptr, 0, src_block ? w.R : nullptr, w.b};
         if (sur_ready) {
           const hipError_t e = hipStreamWaitEvent(st, sur_ready, 0);
           if (e != hipSuccess) return e;
