@@ -63,6 +63,20 @@ __global__ void __launch_bounds__(256) k_sample(Geo g, const Mech *__restrict__ 
       jc[long(p) * NS * NS + s * NS + r] = float(C.dw_dr[s][r] + C.dw_dT[s] * dTc[r] + C.dw_dTv[s] * dTvc[r]);
 }
 
+// sinh in FP32: the Taylor series to y^7 below |y| = 1/2 (truncation below
+// 5e-9 relative), (e - 1/e) / 2 with e = exp(|y|) above (where the
+// difference loses at most one bit): a few ulp, at a fraction of the cost of
+// the library's sinhf; overflows to +-inf where sinhf does
+__device__ __forceinline__ float sinh32(float y) {
+  const float a = fabsf(y);
+  if (a < 0.5f) {
+    const float y2 = y * y;
+    return y * (1.0f + y2 * (1.0f / 6.0f + y2 * (1.0f / 120.0f + y2 * (1.0f / 5040.0f))));
+  }
+  const float e = expf(a);
+  return copysignf(0.5f * (e - 1.0f / e), y);
+}
+
 // One block = 64 cells (4 waves x 16); J = sinh(y) / tau0.
 template <int NS, int NT>
 __global__ void __launch_bounds__(256) k_surrogate(Geo g, const double *__restrict__ prim, SurArgs a,
@@ -101,7 +115,7 @@ __global__ void __launch_bounds__(256) k_surrogate(Geo g, const double *__restri
     const int o0 = 16 * t + 4 * gq;
     f32x4 v;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = sinhf(y[r]) * itau;
+    for (int r = 0; r < 4; ++r) v[r] = sinh32(y[r]) * itau;
     if (!valid) continue;
     if constexpr (CELL_MAJOR && NN % 4 == 0) {
       // a lane's four outputs are consecutive entries of its cell's block and
