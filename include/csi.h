@@ -127,6 +127,18 @@ int csi_set_grid(csi_ctx *ctx, int ni, int nj, const double *x_nodes, const doub
  * CSI_WIDE_MAX_SPECIES, nr > 64 or bad tables. */
 #define CSI_WIDE_MAX_SPECIES 4096
 int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
+/* Residual scheme: 0 (default) first-order HLLE mixture flux with upwinded
+ * species and e_ve fluxes; 1 the second-order scheme of the paper's cylinder
+ * case (Section 3.2): MUSCL reconstruction of (rho_s, u, v, T, Tv) with the
+ * minmod limiter at interior faces (boundary faces first order) and Roe's
+ * flux for the mixture at frozen composition (Roe-averaged u, v, H and
+ * dp/d(rho E); Harten's entropy fix on the acoustic waves), the species and
+ * e_ve carried by the mixture mass flux at the upwind mass fraction / e_ve.
+ * Only the residual changes: the implicit operator keeps its first-order
+ * spectral-radius form.  A non-physical reconstructed state is reported as
+ * CSI_ERR_NONFINITE by the residual or step.  Errors: CSI_ERR_ARG for another
+ * value; CSI_ERR_UNSUPPORTED for 1 on the species-generic kernels. */
+int csi_set_residual_scheme(csi_ctx *ctx, int scheme);
 /* on = 1: the next csi_set_mechanism takes the species-generic kernels for
  * every species count (so that they can be compared with the compiled ones on
  * the same case); on = 0 (the default): only above 32 species.  Errors:

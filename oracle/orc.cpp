@@ -66,6 +66,8 @@ struct orc_ctx {
   // difference F(Q_N + x) - F(Q_N) (coupled and flow parts)
   int flux_diff = 0;
   int fd_bad = -1;  // a cell whose neighbour state plus increment was not physical
+  // residual scheme: 0 first-order HLLE, 1 MUSCL (minmod) + Roe
+  int scheme = 0;
   // dual time stepping: physical time step dt and theta (dt = 0: steady),
   // the time levels Q^n and Q^{n-1}
   double pt_dt = 0.0, pt_theta = 0.0;
@@ -190,6 +192,95 @@ void hlle(const Mech &m, const CellD &L, const CellD &R, double nx, double ny, d
   for (int s = 0; s < ns; ++s) F[s] = fmass * U.P.Y[s];
   for (int k = ns; k < ns + 3; ++k) F[k] = hll(FL[k], FR[k], L.q[k], R.q[k]);
   if (m.two_temp) F[ns + 3] = fmass * U.eve;
+}
+
+// ------------------------------------------- MUSCL + Roe (residual ablation)
+// The second-order residual of the paper's cylinder case (Section 3.2: MUSCL
+// reconstruction with the minmod limiter and Roe's approximate Riemann
+// solver).  Reconstructed: w = (rho_s, u, v, T, Tv) per cell; at interior
+// faces w_face = w_B + 1/2 minmod(w_B - w_A, w_C - w_B) on the side of cell B
+// (A beyond B, C across the face); boundary faces first order.  Roe flux for
+// the mixture (frozen composition) with the species and e_ve carried by the
+// mixture mass flux at the upwind mass fraction / e_ve, as in the HLLE flux.
+double minmod(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return std::fabs(a) < std::fabs(b) ? a : b;
+}
+
+// dp/d(rho E) at fixed other stored variables (complex step)
+double eos_beta(const Mech &m, const double *q) {
+  const int nv = m.nv(), ns = m.ns;
+  cplx qc[MAXV];
+  for (int k = 0; k < nv; ++k) qc[k] = q[k];
+  const double h = CSTEP * std::max(std::fabs(q[ns + 2]), 1.0);
+  qc[ns + 2] += cplx(0.0, h);
+  Prim<cplx> Pc;
+  recover<cplx>(m, qc, Pc);
+  return Pc.p.imag() / h;
+}
+
+bool muscl_state(const Mech &m, const CellD &A, const CellD &B, const CellD &C, CellD &out) {
+  const int ns = m.ns;
+  auto rec = [&](double a, double b, double cc) { return b + 0.5 * minmod(b - a, cc - b); };
+  double rs[MAXS], q[MAXV];
+  for (int s = 0; s < ns; ++s) rs[s] = rec(A.P.rs[s], B.P.rs[s], C.P.rs[s]);
+  const double u = rec(A.P.u, B.P.u, C.P.u), v = rec(A.P.v, B.P.v, C.P.v);
+  const double T = rec(A.P.T, B.P.T, C.P.T);
+  const double Tv = m.two_temp ? rec(A.P.Tv, B.P.Tv, C.P.Tv) : T;
+  prim_to_cons<double>(m, rs, u, v, T, Tv, q);
+  return make_cell(m, q, out);
+}
+
+// Roe average with weights w = sqrt(rho_L) / (sqrt(rho_L) + sqrt(rho_R)):
+// u, v, H, beta = dp/d(rho E) averaged; the sound speed from
+// c^2 = w c_L^2 + (1 - w) c_R^2 + beta w (1 - w) |V_R - V_L|^2 / 2, which is
+// Roe's average (gamma - 1)(H - |V|^2/2 - h_f) for a calorically perfect gas
+// of fixed composition.  The waves moving at u.n (entropy, composition and
+// vibrational energy jumps of a real-gas mixture lumped into one) carry the
+// part of the rho E jump the acoustic and shear waves leave: a2 e2 =
+// d(rho E) - H dp / c^2 - rho V.dV, so the wave decomposition reproduces the
+// jump of every mixture variable and, with the sqrt(rho) averages, the flux
+// jump too (Roe's property, for any equation of state); for a calorically
+// perfect gas of fixed composition e2 = H - c^2 / beta, Roe's own value.
+// Harten's entropy fix (delta = c / 10) on the acoustic waves.
+void roe(const Mech &m, const CellD &L, const CellD &R, double nx, double ny, double *F) {
+  const int ns = m.ns;
+  double FL[MAXV], FR[MAXV];
+  phys_flux<double>(m, L.q, L.P, nx, ny, FL);
+  phys_flux<double>(m, R.q, R.P, nx, ny, FR);
+  const double sL = std::sqrt(L.P.rho), sR = std::sqrt(R.P.rho), w = sL / (sL + sR), wr = 1.0 - w;
+  const double u = w * L.P.u + wr * R.P.u, v = w * L.P.v + wr * R.P.v, H = w * L.H + wr * R.H;
+  const double beta = w * eos_beta(m, L.q) + wr * eos_beta(m, R.q);
+  const double dVx = R.P.u - L.P.u, dVy = R.P.v - L.P.v;
+  const double cL2 = L.c * L.c, cR2 = R.c * R.c;
+  double c2 = w * cL2 + wr * cR2 + 0.5 * beta * w * wr * (dVx * dVx + dVy * dVy);
+  c2 = std::max(c2, 1e-6 * std::min(cL2, cR2));
+  const double c = std::sqrt(c2), rho = sL * sR;
+  const double un = u * nx + v * ny, ut = -u * ny + v * nx;
+  const double unL = L.P.u * nx + L.P.v * ny, unR = R.P.u * nx + R.P.v * ny;
+  const double utL = -L.P.u * ny + L.P.v * nx, utR = -R.P.u * ny + R.P.v * nx;
+  const double dp = R.P.p - L.P.p, dun = unR - unL, dut = utR - utL, drho = R.P.rho - L.P.rho;
+  const double a1 = (dp - rho * c * dun) / (2.0 * c2), a3 = (dp + rho * c * dun) / (2.0 * c2);
+  const double a2 = drho - dp / c2, at = rho * dut;
+  const double delta = 0.1 * c;
+  auto fix = [&](double l) {
+    const double a = std::fabs(l);
+    return a < delta ? (l * l + delta * delta) / (2.0 * delta) : a;
+  };
+  const double l1 = fix(un - c), l2 = std::fabs(un), l3 = fix(un + c);
+  const double a2e2 = (R.q[ns + 2] - L.q[ns + 2]) - H * dp / c2 - rho * (u * dVx + v * dVy);
+  const double D0 = l1 * a1 + l2 * a2 + l3 * a3;
+  const double Dx = l1 * a1 * (u - c * nx) + l2 * (a2 * u - at * ny) + l3 * a3 * (u + c * nx);
+  const double Dy = l1 * a1 * (v - c * ny) + l2 * (a2 * v + at * nx) + l3 * a3 * (v + c * ny);
+  const double DE = l1 * a1 * (H - un * c) + l2 * (a2e2 + at * ut) + l3 * a3 * (H + un * c);
+  const double mL = L.P.rho * unL, mR = R.P.rho * unR;
+  const double fmass = 0.5 * (mL + mR) - 0.5 * D0;
+  const CellD &Up = fmass >= 0.0 ? L : R;
+  for (int s = 0; s < ns; ++s) F[s] = fmass * Up.P.Y[s];
+  F[ns] = 0.5 * (FL[ns] + FR[ns]) - 0.5 * Dx;
+  F[ns + 1] = 0.5 * (FL[ns + 1] + FR[ns + 1]) - 0.5 * Dy;
+  F[ns + 2] = 0.5 * (FL[ns + 2] + FR[ns + 2]) - 0.5 * DE;
+  if (m.two_temp) F[ns + 3] = fmass * Up.eve;
 }
 
 struct FaceVals {
@@ -420,6 +511,12 @@ int orc_set_option(orc_ctx *c, const char *name, double value) {
   }
   if (n == "flux_diff") {
     c->flux_diff = value != 0.0;
+    return 0;
+  }
+  if (n == "residual_scheme") {
+    if (value != 0.0 && value != 1.0) return c->fail(-1, "residual_scheme must be 0 or 1");
+    c->scheme = int(value);
+    c->has_res = false;
     return 0;
   }
   return c->fail(-1, "unknown option " + n);
@@ -661,8 +758,23 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
     Face &F = c->fI[c->fii(I, j)];
     F.S = c->fi_S[c->fii(I, j)]; F.nx = c->fi_nx[c->fii(I, j)]; F.ny = c->fi_ny[c->fii(I, j)];
     const CellD &L = cell(I - 1, j), &R = cell(I, j);
-    hlle(m, L, R, F.nx, F.ny, F.F);
     bool interior = I > 0 && I < ni;
+    if (c->scheme == 1) {
+      if (interior) {
+        CellD Lf, Rf;
+        if (!muscl_state(m, cell(I - 2, j), L, R, Lf) || !muscl_state(m, cell(I + 1, j), R, L, Rf)) {
+#pragma omp critical
+          bad = (bad < 0 || c->ci(I, j) < bad) ? c->ci(I, j) : bad;
+          roe(m, L, R, F.nx, F.ny, F.F);
+        } else {
+          roe(m, Lf, Rf, F.nx, F.ny, F.F);
+        }
+      } else {
+        roe(m, L, R, F.nx, F.ny, F.F);
+      }
+    } else {
+      hlle(m, L, R, F.nx, F.ny, F.F);
+    }
     double VL = interior ? c->V[c->ci(I - 1, j)] : 0.0, VR = interior ? c->V[c->ci(I, j)] : 0.0;
     int pin = I == 0 ? c->ci(0, j) : c->ci(ni - 1, j);
     radii(F, L, R, VL, VR, interior, I == 0 ? cell(0, j) : cell(ni - 1, j), c->V[pin]);
@@ -680,8 +792,23 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
     Face &F = c->fJ[c->fji(i, J)];
     F.S = c->fj_S[c->fji(i, J)]; F.nx = c->fj_nx[c->fji(i, J)]; F.ny = c->fj_ny[c->fji(i, J)];
     const CellD &L = cell(i, J - 1), &R = cell(i, J);
-    hlle(m, L, R, F.nx, F.ny, F.F);
     bool interior = J > 0 && J < nj;
+    if (c->scheme == 1) {
+      if (interior) {
+        CellD Lf, Rf;
+        if (!muscl_state(m, cell(i, J - 2), L, R, Lf) || !muscl_state(m, cell(i, J + 1), R, L, Rf)) {
+#pragma omp critical
+          bad = (bad < 0 || c->ci(i, J) < bad) ? c->ci(i, J) : bad;
+          roe(m, L, R, F.nx, F.ny, F.F);
+        } else {
+          roe(m, Lf, Rf, F.nx, F.ny, F.F);
+        }
+      } else {
+        roe(m, L, R, F.nx, F.ny, F.F);
+      }
+    } else {
+      hlle(m, L, R, F.nx, F.ny, F.F);
+    }
     double VL = interior ? c->V[c->ci(i, J - 1)] : 0.0, VR = interior ? c->V[c->ci(i, J)] : 0.0;
     int pin = J == 0 ? c->ci(i, 0) : c->ci(i, nj - 1);
     radii(F, L, R, VL, VR, interior, J == 0 ? cell(i, 0) : cell(i, nj - 1), c->V[pin]);
@@ -721,6 +848,7 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
       c->qw[i] = -qn;
     }
   }
+  if (bad >= 0) return c->fail(-4, "non-physical reconstructed face state next to cell " + std::to_string(bad));
   // cell residual, time step, sources, Jacobians, diagonal blocks
   c->R.assign(size_t(nv) * N, 0.0); c->dtau.assign(N, 0.0); c->src.assign(size_t(nv) * N, 0.0);
   c->dK.assign(N, 0.0); c->dF.assign(N, 0.0); c->dC.assign(N, 0.0);
@@ -1323,6 +1451,24 @@ int orc_point_hlle(orc_ctx *c, const double *qL, const double *qR, double nx, do
   CellD L, R;
   if (!make_cell(c->m, qL, L) || !make_cell(c->m, qR, R)) return c->fail(-4, "non-physical point state");
   hlle(c->m, L, R, nx, ny, F);
+  return 0;
+}
+
+int orc_point_roe(orc_ctx *c, const double *qL, const double *qR, double nx, double ny, double *F) {
+  if (!c || !c->has_mech) return -1;
+  CellD L, R;
+  if (!make_cell(c->m, qL, L) || !make_cell(c->m, qR, R)) return c->fail(-4, "non-physical point state");
+  roe(c->m, L, R, nx, ny, F);
+  return 0;
+}
+
+int orc_point_muscl(orc_ctx *c, const double *qA, const double *qB, const double *qC, double *qf) {
+  if (!c || !c->has_mech) return -1;
+  CellD A, B, C, out;
+  if (!make_cell(c->m, qA, A) || !make_cell(c->m, qB, B) || !make_cell(c->m, qC, C))
+    return c->fail(-4, "non-physical point state");
+  if (!muscl_state(c->m, A, B, C, out)) return c->fail(-4, "non-physical reconstructed state");
+  for (int k = 0; k < c->m.nv(); ++k) qf[k] = out.q[k];
   return 0;
 }
 

@@ -53,7 +53,9 @@ int orc_create(orc_ctx **ctx);
 void orc_destroy(orc_ctx *ctx);
 const char *orc_last_error(const orc_ctx *ctx);
 int orc_set_threads(orc_ctx *ctx, int n);
-/* named options: "jc_fixed_qf" (0: split species block at fixed T, Tv;
+/* named options: "residual_scheme" (0: first-order HLLE; 1: MUSCL with the
+ * minmod limiter on (rho_s, u, v, T, Tv) at interior faces and the Roe flux);
+ * "jc_fixed_qf" (0: split species block at fixed T, Tv;
  * 1: at fixed momenta and energies; 2: at fixed velocities and internal
  * energy densities, the temperatures following; 3: as 2 with Tv held; the
  * default after orc_set_mechanism is 2 in one temperature and 0 in two);
@@ -113,6 +115,10 @@ int orc_point_flux_jacobian(orc_ctx *ctx, const double *q, double nx, double ny,
 int orc_point_flux(orc_ctx *ctx, const double *q, double nx, double ny, double *F);
 /* HLLE face flux between left state qL and right state qR, unit normal (nx, ny) from L to R */
 int orc_point_hlle(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double *F);
+/* Roe face flux (MUSCL + Roe residual scheme) between states qL and qR */
+int orc_point_roe(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double *F);
+/* MUSCL (minmod) face state on the side of cell B: A beyond B, C across the face */
+int orc_point_muscl(orc_ctx *ctx, const double *qA, const double *qB, const double *qC, double *qf);
 /* off-diagonal neighbour term at state q: mode 0 coupled (x in z), 1 flow part
  * (x in Q_F at frozen Y); fd 0: A(n) x, fd 1: F(q + x).n - F(q).n */
 int orc_point_offdiag(orc_ctx *ctx, const double *q, double nx, double ny, int mode, int fd, const double *x,

@@ -259,6 +259,21 @@ class Oracle:
         self._check(self.L.orc_point_hlle(self.ctx, pl, pr, C.c_double(nx), C.c_double(ny), F.ctypes.data_as(_dp)))
         return F
 
+    def point_roe(self, qL, qR, nx, ny):
+        F = np.zeros(self.mech.nv)
+        a, pl = _d(qL)
+        b, pr = _d(qR)
+        self._check(self.L.orc_point_roe(self.ctx, pl, pr, C.c_double(nx), C.c_double(ny), F.ctypes.data_as(_dp)))
+        return F
+
+    def point_muscl(self, qA, qB, qC):
+        qf = np.zeros(self.mech.nv)
+        a, pa = _d(qA)
+        b, pb = _d(qB)
+        c, pc = _d(qC)
+        self._check(self.L.orc_point_muscl(self.ctx, pa, pb, pc, qf.ctypes.data_as(_dp)))
+        return qf
+
     def point_flux_jacobian(self, q, nx, ny):
         nv = self.mech.nv
         A = np.zeros((nv, nv))

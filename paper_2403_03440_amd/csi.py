@@ -34,7 +34,7 @@ EXPORTED = ["csi_create", "csi_destroy", "csi_last_error", "csi_set_grid", "csi_
             "csi_mlp_train_step", "csi_sample_jacobians", "csi_set_surrogate", "csi_mlp_forward_noalloc",
             "csi_set_species_jacobian", "csi_set_physical_time", "csi_advance_time",
             "csi_set_time_levels", "csi_set_offdiag", "csi_mlp_train_epoch", "csi_set_species_generic",
-            "csi_block_inverse", "csi_block_inverse_work"]
+            "csi_block_inverse", "csi_block_inverse_work", "csi_set_residual_scheme"]
 WIDE_MAX_SPECIES = 4096
 PHASES = ["prim", "faces", "cell", "block", "norms", "sweep_fwd", "sweep_bwd", "update"]
 
@@ -311,6 +311,10 @@ class Solver:
         a, pa = _d(qn)
         b, pb = _d(qnm1)
         self._check(self.L.csi_set_time_levels(self.ctx, pa, pb, 0))
+
+    def set_residual_scheme(self, scheme):
+        """0: first-order HLLE; 1: MUSCL (minmod) + Roe."""
+        self._check(self.L.csi_set_residual_scheme(self.ctx, scheme))
 
     def set_species_jacobian(self, reading):
         """0: split species block at fixed T, Tv; 1: at fixed velocities and

@@ -129,6 +129,8 @@ struct csi_ctx {
   double pt_a = 0.0, pt_b = 0.0;
   // off-diagonal operator: 0 linear Jacobian-vector products, 1 flux differences
   int fdiff = 0;
+  // residual scheme: 0 first-order HLLE, 1 MUSCL (minmod) + Roe
+  int scheme = 0;
   int jc_flag() const { return jc_reading == 0 ? 0 : (jc_reading == 1 ? 8 : 8 | 16); }
 
   int nv() const { return ns + 3 + (nt == 2 ? 1 : 0); }
@@ -462,6 +464,7 @@ int csi_bind_workspace(csi_ctx *c, void *dev, size_t bytes) {
   w.hist_max = HIST_MAX;
   Geo &g = c->g;
   g.ni = c->ni; g.nj = c->nj; g.N = c->N; g.NP = (c->ni + 2) * (c->nj + 2); g.bc_mode = c->bc_mode; g.Tw = c->Tw;
+  g.scheme = c->scheme;
   g.V = w.V; g.xc = w.xc; g.yc = w.yc; g.xn = w.xn; g.yn = w.yn;
   g.fi_nx = w.fi_nx; g.fi_ny = w.fi_ny; g.fi_S = w.fi_S; g.fj_nx = w.fj_nx; g.fj_ny = w.fj_ny; g.fj_S = w.fj_S;
   hipStream_t st = c->stream;
@@ -867,6 +870,18 @@ int csi_set_offdiag(csi_ctx *c, int op) {
   c->fdiff = op;
   c->w.fdiff = op;
   if (op == 1) return csi_set_sweep(c, 0);  // flux differences run in the per-hyperplane sweeps
+  c->has_dq = false;
+  return CSI_OK;
+}
+
+int csi_set_residual_scheme(csi_ctx *c, int scheme) {
+  if (!c) return CSI_ERR_ARG;
+  if (scheme != 0 && scheme != 1) return c->fail(CSI_ERR_ARG, "residual scheme must be 0 or 1");
+  if (c->wide && scheme != 0)
+    return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels have the first-order residual only");
+  c->scheme = scheme;
+  c->g.scheme = scheme;
+  c->has_res = false;
   c->has_dq = false;
   return CSI_OK;
 }

@@ -10,6 +10,7 @@ namespace csi {
 // ------------------------------------------------------------ workspace view
 struct Geo {
   int ni, nj, N, NP, bc_mode;
+  int scheme;  // residual: 0 first-order HLLE, 1 MUSCL (minmod) + Roe
   double Tw;
   const double *V, *xc, *yc, *xn, *yn;
   const double *fi_nx, *fi_ny, *fi_S;  // i-faces, index j*(ni+1)+I, normal towards +i
@@ -148,6 +149,123 @@ __device__ __forceinline__ void hlle_flux(const FaceState<NS> &L, const FaceStat
   if (NT == 2) F[NS + 3] = fm * U.eve;
 }
 
+// ------------------------------------------------ MUSCL (minmod) + Roe
+// The second-order residual of the paper's cylinder case (Section 3.2),
+// built as an ablation: w = (rho_s, u, v, T, Tv) reconstructed per side at
+// interior faces, w_face = w_B + 1/2 minmod(w_B - w_A, w_C - w_B) (A beyond
+// the side's cell B, C across the face), boundary faces first order; the Roe
+// flux of the mixture at frozen composition, species and e_ve carried by the
+// mixture mass flux at the upwind mass fraction / e_ve as in hlle_flux.
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return fabs(a) < fabs(b) ? a : b;
+}
+
+template <int NS> struct RoeState {
+  double rho, u, v, p, c, H, rE, eve, beta, Y[NS];
+};
+
+template <int NS>
+__device__ __forceinline__ void roe_state_cell(const double *prim, size_t NP, int pc, RoeState<NS> &s) {
+  s.rho = prim[F_RHO * NP + pc]; s.u = prim[F_U * NP + pc]; s.v = prim[F_V * NP + pc];
+  s.p = prim[F_P * NP + pc]; s.c = prim[F_C * NP + pc]; s.H = prim[F_H * NP + pc];
+  s.rE = prim[F_RE * NP + pc]; s.eve = prim[F_EVE * NP + pc]; s.beta = prim[F_PE * NP + pc];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s.Y[k] = prim[(PF<NS>::Y + k) * NP + pc];
+}
+
+// the face state on the side of cell pB (pA beyond it, pC across the face)
+template <int NS, int NT>
+__device__ __forceinline__ bool roe_state_muscl(const Mech &m, const double *prim, size_t NP, int pA, int pB, int pC,
+                                                RoeState<NS> &s) {
+  auto rec = [&](double a, double b, double c) { return b + 0.5 * minmod(b - a, c - b); };
+  auto fld = [&](int f, int pc) { return prim[size_t(f) * NP + pc]; };
+  const double rA = fld(F_RHO, pA), rB = fld(F_RHO, pB), rC = fld(F_RHO, pC);
+  double rs[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int f = PF<NS>::Y + k;
+    rs[k] = rec(rA * fld(f, pA), rB * fld(f, pB), rC * fld(f, pC));
+  }
+  const double u = rec(fld(F_U, pA), fld(F_U, pB), fld(F_U, pC));
+  const double v = rec(fld(F_V, pA), fld(F_V, pB), fld(F_V, pC));
+  const double T = rec(fld(F_T, pA), fld(F_T, pB), fld(F_T, pC));
+  const double Tv = NT == 2 ? rec(fld(F_TV, pA), fld(F_TV, pB), fld(F_TV, pC)) : T;
+  double q[Dims<NS, NT>::nv];
+  q_from_prim<NS, NT>(m, rs, u, v, T, Tv, q);
+  Prim<NS, NT> P;
+  if (!prim_from_q<NS, NT>(m, q, P, T, Tv)) return false;
+  s.rho = P.rho; s.u = P.u; s.v = P.v; s.p = P.p; s.c = P.c; s.H = P.H; s.rE = P.rE; s.eve = P.eve;
+  s.beta = P.pE;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s.Y[k] = P.Y[k];
+  return true;
+}
+
+// Roe average with weights w = sqrt(rho_L) / (sqrt(rho_L) + sqrt(rho_R)) of
+// u, v, H and beta = dp/d(rho E); c^2 = w c_L^2 + (1 - w) c_R^2 +
+// beta w (1 - w) |V_R - V_L|^2 / 2 (Roe's average for a calorically perfect
+// gas of fixed composition); the waves at u.n carry the rest of the rho E
+// jump, a2 e2 = d(rho E) - H dp / c^2 - rho V.dV, which keeps Roe's property
+// for a real-gas mixture (e2 = H - c^2 / beta for a perfect gas); Harten's
+// entropy fix (delta = c / 10) on the acoustic waves
+template <int NS, int NT>
+__device__ __forceinline__ void roe_flux(const RoeState<NS> &L, const RoeState<NS> &R, double nx, double ny,
+                                         double *F) {
+  const double unL = L.u * nx + L.v * ny, unR = R.u * nx + R.v * ny;
+  const double sL = sqrt(L.rho), sR = sqrt(R.rho), w = sL / (sL + sR), wr = 1.0 - w;
+  const double u = w * L.u + wr * R.u, v = w * L.v + wr * R.v, H = w * L.H + wr * R.H;
+  const double beta = w * L.beta + wr * R.beta;
+  const double dVx = R.u - L.u, dVy = R.v - L.v;
+  const double cL2 = L.c * L.c, cR2 = R.c * R.c;
+  double c2 = w * cL2 + wr * cR2 + 0.5 * beta * w * wr * (dVx * dVx + dVy * dVy);
+  c2 = fmax(c2, 1e-6 * fmin(cL2, cR2));
+  const double c = sqrt(c2), rho = sL * sR;
+  const double un = u * nx + v * ny, ut = -u * ny + v * nx;
+  const double utL = -L.u * ny + L.v * nx, utR = -R.u * ny + R.v * nx;
+  const double dp = R.p - L.p, dun = unR - unL, dut = utR - utL, drho = R.rho - L.rho;
+  const double a1 = (dp - rho * c * dun) / (2.0 * c2), a3 = (dp + rho * c * dun) / (2.0 * c2);
+  const double a2 = drho - dp / c2, at = rho * dut;
+  const double delta = 0.1 * c;
+  auto fix = [&](double l) {
+    const double a = fabs(l);
+    return a < delta ? (l * l + delta * delta) / (2.0 * delta) : a;
+  };
+  const double l1 = fix(un - c), l2 = fabs(un), l3 = fix(un + c);
+  const double a2e2 = (R.rE - L.rE) - H * dp / c2 - rho * (u * dVx + v * dVy);
+  const double D0 = l1 * a1 + l2 * a2 + l3 * a3;
+  const double Dx = l1 * a1 * (u - c * nx) + l2 * (a2 * u - at * ny) + l3 * a3 * (u + c * nx);
+  const double Dy = l1 * a1 * (v - c * ny) + l2 * (a2 * v + at * nx) + l3 * a3 * (v + c * ny);
+  const double DE = l1 * a1 * (H - un * c) + l2 * (a2e2 + at * ut) + l3 * a3 * (H + un * c);
+  const double mL = L.rho * unL, mR = R.rho * unR;
+  const double fm = 0.5 * (mL + mR) - 0.5 * D0;
+  const RoeState<NS> &U = fm >= 0.0 ? L : R;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) F[s] = fm * U.Y[s];
+  F[NS] = 0.5 * ((L.rho * L.u * unL + L.p * nx) + (R.rho * R.u * unR + R.p * nx)) - 0.5 * Dx;
+  F[NS + 1] = 0.5 * ((L.rho * L.v * unL + L.p * ny) + (R.rho * R.v * unR + R.p * ny)) - 0.5 * Dy;
+  F[NS + 2] = 0.5 * ((L.rE + L.p) * unL + (R.rE + R.p) * unR) - 0.5 * DE;
+  if (NT == 2) F[NS + 3] = fm * U.eve;
+}
+
+// the inviscid face flux of the MUSCL + Roe scheme; pLL / pRR: the cells
+// beyond pL / pR (used at interior faces); false on a non-physical
+// reconstructed state (the flux is then the first-order Roe flux)
+template <int NS, int NT>
+__device__ __forceinline__ bool muscl_roe_flux(const Mech &m, const double *prim, size_t NP, int pLL, int pL, int pR,
+                                               int pRR, bool interior, double nx, double ny, double *F) {
+  RoeState<NS> L, R;
+  bool ok = true;
+  if (interior)
+    ok = roe_state_muscl<NS, NT>(m, prim, NP, pLL, pL, pR, L) && roe_state_muscl<NS, NT>(m, prim, NP, pRR, pR, pL, R);
+  if (!interior || !ok) {
+    roe_state_cell<NS>(prim, NP, pL, L);
+    roe_state_cell<NS>(prim, NP, pR, R);
+  }
+  roe_flux<NS, NT>(L, R, nx, ny, F);
+  return ok;
+}
+
 // gradient from the two diagonals of the diamond: d1.g = D1, d2.g = D2
 __device__ __forceinline__ void diamond_grad(double d1x, double d1y, double d2x, double d2y, double D1, double D2,
                                              double &gx, double &gy) {
@@ -251,11 +369,12 @@ __device__ __forceinline__ void radii(const Geo &g, const double *prim, int pL, 
   rad[R_LVK] = nK * S / Vf;
 }
 
-// i-faces: (I, j), I in [0, ni], j in [0, nj)
-template <int NS, int NT>
+// i-faces: (I, j), I in [0, ni], j in [0, nj); SCH: the residual scheme
+// (0 first-order HLLE, 1 MUSCL + Roe)
+template <int NS, int NT, int SCH>
 __global__ void __launch_bounds__(256) k_face_i(Geo g, const Mech *__restrict__ mech, const double *__restrict__ prim,
                                                 double *__restrict__ Fi, double *__restrict__ Ri,
-                                                const int *__restrict__ done) {
+                                                const int *__restrict__ done, int *__restrict__ bad) {
   using D = Dims<NS, NT>;
   if (done && *done) return;
   int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,8 +388,14 @@ __global__ void __launch_bounds__(256) k_face_i(Geo g, const Mech *__restrict__ 
   load_face_state<NS>(prim, NP, pL, L);
   load_face_state<NS>(prim, NP, pR, R);
   double F[D::nv];
-  hlle_flux<NS, NT>(L, R, nx, ny, F);
   bool interior = I > 0 && I < g.ni;
+  if constexpr (SCH == 1) {
+    if (!muscl_roe_flux<NS, NT>(*mech, prim, NP, interior ? padc(g, I - 2, j) : pL, pL, pR,
+                                interior ? padc(g, I + 1, j) : pR, interior, nx, ny, F) && bad)
+      atomicMin(bad, j * g.ni + (I < g.ni ? I : g.ni - 1));
+  } else {
+    hlle_flux<NS, NT>(L, R, nx, ny, F);
+  }
   double rad[R_N];
   int cin = j * g.ni + (I == 0 ? 0 : g.ni - 1);
   radii<NS, NT>(g, prim, pL, pR, interior, padc(g, I == 0 ? 0 : g.ni - 1, j), interior ? g.V[j * g.ni + I - 1] : 0.0,
@@ -289,10 +414,11 @@ __global__ void __launch_bounds__(256) k_face_i(Geo g, const Mech *__restrict__ 
 }
 
 // j-faces: (i, J), i in [0, ni), J in [0, nj]; J = 0 is the wall in bc_mode 0
-template <int NS, int NT>
+template <int NS, int NT, int SCH>
 __global__ void __launch_bounds__(256) k_face_j(Geo g, const Mech *__restrict__ mech, const double *__restrict__ prim,
                                                 double *__restrict__ Fj, double *__restrict__ Rj,
-                                                double *__restrict__ qw, const int *__restrict__ done) {
+                                                double *__restrict__ qw, const int *__restrict__ done,
+                                                int *__restrict__ bad) {
   using D = Dims<NS, NT>;
   if (done && *done) return;
   int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,8 +433,14 @@ __global__ void __launch_bounds__(256) k_face_j(Geo g, const Mech *__restrict__ 
   load_face_state<NS>(prim, NP, pL, L);
   load_face_state<NS>(prim, NP, pR, R);
   double F[D::nv];
-  hlle_flux<NS, NT>(L, R, nx, ny, F);
   bool interior = J > 0 && J < g.nj;
+  if constexpr (SCH == 1) {
+    if (!muscl_roe_flux<NS, NT>(m, prim, NP, interior ? padc(g, i, J - 2) : pL, pL, pR,
+                                interior ? padc(g, i, J + 1) : pR, interior, nx, ny, F) && bad)
+      atomicMin(bad, (J < g.nj ? J : g.nj - 1) * g.ni + i);
+  } else {
+    hlle_flux<NS, NT>(L, R, nx, ny, F);
+  }
   double rad[R_N];
   int cin = (J == 0 ? 0 : g.nj - 1) * g.ni + i;
   radii<NS, NT>(g, prim, pL, pR, interior, padc(g, i, J == 0 ? 0 : g.nj - 1), interior ? g.V[(J - 1) * g.ni + i] : 0.0,

@@ -121,12 +121,21 @@ template <int NS, int NT> class Runner : public IRunner {
 
   hipError_t faces(const Geo &g, const WS &w, hipStream_t st, bool stoppable) override {
     const int *done = stoppable ? w.flags + FL_DONE : nullptr;
+    // (the streaming face kernels have the first-order HLLE residual only)
     if constexpr (NT == 1 && NS >= STREAM_NS_MIN)
-      return launch_stream_faces(g, w.mview, w.prim, w.Fi, w.Ri, w.Fj, w.Rj, w.qw, done, st);
-    hipLaunchKernelGGL((k_face_i<NS, NT>), dim3(nblocks(long(g.ni + 1) * g.nj)), dim3(256), 0, st, g, w.mech, w.prim,
-                       w.Fi, w.Ri, done);
-    hipLaunchKernelGGL((k_face_j<NS, NT>), dim3(nblocks(long(g.ni) * (g.nj + 1))), dim3(256), 0, st, g, w.mech,
-                       w.prim, w.Fj, w.Rj, w.qw, done);
+      if (g.scheme == 0) return launch_stream_faces(g, w.mview, w.prim, w.Fi, w.Ri, w.Fj, w.Rj, w.qw, done, st);
+    const dim3 bi(nblocks(long(g.ni + 1) * g.nj)), bj(nblocks(long(g.ni) * (g.nj + 1)));
+    if (g.scheme == 1) {
+      hipLaunchKernelGGL((k_face_i<NS, NT, 1>), bi, dim3(256), 0, st, g, w.mech, w.prim, w.Fi, w.Ri, done,
+                         w.flags + FL_BAD);
+      hipLaunchKernelGGL((k_face_j<NS, NT, 1>), bj, dim3(256), 0, st, g, w.mech, w.prim, w.Fj, w.Rj, w.qw, done,
+                         w.flags + FL_BAD);
+    } else {
+      hipLaunchKernelGGL((k_face_i<NS, NT, 0>), bi, dim3(256), 0, st, g, w.mech, w.prim, w.Fi, w.Ri, done,
+                         w.flags + FL_BAD);
+      hipLaunchKernelGGL((k_face_j<NS, NT, 0>), bj, dim3(256), 0, st, g, w.mech, w.prim, w.Fj, w.Rj, w.qw, done,
+                         w.flags + FL_BAD);
+    }
     return hipGetLastError();
   }
 
