@@ -131,8 +131,10 @@ int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
  * species and e_ve fluxes; 1 the second-order scheme of the paper's cylinder
  * case (Section 3.2): MUSCL reconstruction of (rho_s, u, v, T, Tv) with the
  * minmod limiter at interior faces (boundary faces first order) and Roe's
- * flux for the mixture at frozen composition (Roe-averaged u, v, H and
- * dp/d(rho E); Harten's entropy fix on the acoustic waves), the species and
+ * flux for the mixture (Roe-averaged u, v, H and dp/d(rho E); the waves at
+ * u.n carry the rest of the rho E jump, which keeps Roe's property for a
+ * real-gas mixture; Harten's entropy fix on the acoustic waves; Sanders,
+ * Morano and Druguet's H-correction against the carbuncle), the species and
  * e_ve carried by the mixture mass flux at the upwind mass fraction / e_ve.
  * Only the residual changes: the implicit operator keeps its first-order
  * spectral-radius form.  A non-physical reconstructed state is reported as

@@ -242,8 +242,9 @@ bool muscl_state(const Mech &m, const CellD &A, const CellD &B, const CellD &C, 
 // jump of every mixture variable and, with the sqrt(rho) averages, the flux
 // jump too (Roe's property, for any equation of state); for a calorically
 // perfect gas of fixed composition e2 = H - c^2 / beta, Roe's own value.
-// Harten's entropy fix (delta = c / 10) on the acoustic waves.
-void roe(const Mech &m, const CellD &L, const CellD &R, double nx, double ny, double *F) {
+// Harten's entropy fix (delta = c / 10) on the acoustic waves.  eta: a floor
+// on every wave speed (the H-correction below; 0 for none).
+void roe(const Mech &m, const CellD &L, const CellD &R, double nx, double ny, double eta, double *F) {
   const int ns = m.ns;
   double FL[MAXV], FR[MAXV];
   phys_flux<double>(m, L.q, L.P, nx, ny, FL);
@@ -267,7 +268,7 @@ void roe(const Mech &m, const CellD &L, const CellD &R, double nx, double ny, do
     const double a = std::fabs(l);
     return a < delta ? (l * l + delta * delta) / (2.0 * delta) : a;
   };
-  const double l1 = fix(un - c), l2 = std::fabs(un), l3 = fix(un + c);
+  const double l1 = std::max(fix(un - c), eta), l2 = std::max(std::fabs(un), eta), l3 = std::max(fix(un + c), eta);
   const double a2e2 = (R.q[ns + 2] - L.q[ns + 2]) - H * dp / c2 - rho * (u * dVx + v * dVy);
   const double D0 = l1 * a1 + l2 * a2 + l3 * a3;
   const double Dx = l1 * a1 * (u - c * nx) + l2 * (a2 * u - at * ny) + l3 * a3 * (u + c * nx);
@@ -281,6 +282,17 @@ void roe(const Mech &m, const CellD &L, const CellD &R, double nx, double ny, do
   F[ns + 1] = 0.5 * (FL[ns + 1] + FR[ns + 1]) - 0.5 * Dy;
   F[ns + 2] = 0.5 * (FL[ns + 2] + FR[ns + 2]) - 0.5 * DE;
   if (m.two_temp) F[ns + 3] = fmass * Up.eve;
+}
+
+// The H-correction of Sanders, Morano and Druguet against the carbuncle of
+// Roe's flux at a shock aligned with the grid: eta of a face is half the
+// largest jump of a characteristic speed across it, (|un_R - un_L| +
+// |c_R - c_L|) / 2 from the two cells' states, and a face's wave speeds are
+// floored by the largest eta among itself and the four faces of the other
+// family that share an edge with it.
+double eta_face(const CellD &L, const CellD &R, double nx, double ny) {
+  const double unL = L.P.u * nx + L.P.v * ny, unR = R.P.u * nx + R.P.v * ny;
+  return 0.5 * (std::fabs(unR - unL) + std::fabs(R.c - L.c));
 }
 
 struct FaceVals {
@@ -692,6 +704,30 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
     }
   }
   auto cell = [&](int i, int j) -> const CellD & { return c->cells[c->pc(i, j)]; };
+  // the H-correction's eta of every face (MUSCL + Roe only)
+  std::vector<double> etaI, etaJ;
+  if (c->scheme == 1) {
+    etaI.assign(size_t(ni + 1) * nj, 0.0);
+    etaJ.assign(size_t(ni) * (nj + 1), 0.0);
+    for (int j = 0; j < nj; ++j)
+      for (int I = 0; I <= ni; ++I)
+        etaI[c->fii(I, j)] = eta_face(cell(I - 1, j), cell(I, j), c->fi_nx[c->fii(I, j)], c->fi_ny[c->fii(I, j)]);
+    for (int J = 0; J <= nj; ++J)
+      for (int i = 0; i < ni; ++i)
+        etaJ[c->fji(i, J)] = eta_face(cell(i, J - 1), cell(i, J), c->fj_nx[c->fji(i, J)], c->fj_ny[c->fji(i, J)]);
+  }
+  auto eta_i = [&](int I, int j) {
+    double e = etaI[c->fii(I, j)];
+    for (int i = I - 1; i <= I; ++i)
+      if (i >= 0 && i < ni) e = std::max(e, std::max(etaJ[c->fji(i, j)], etaJ[c->fji(i, j + 1)]));
+    return e;
+  };
+  auto eta_j = [&](int i, int J) {
+    double e = etaJ[c->fji(i, J)];
+    for (int j = J - 1; j <= J; ++j)
+      if (j >= 0 && j < nj) e = std::max(e, std::max(etaI[c->fii(i, j)], etaI[c->fii(i + 1, j)]));
+    return e;
+  };
   // node values for the diamond gradients: 0 u, 1 v, 2 T, 3 Tv, 4+s Y_s
   auto cellvar = [&](const CellD &C, int var) -> double {
     switch (var) {
@@ -765,12 +801,12 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
         if (!muscl_state(m, cell(I - 2, j), L, R, Lf) || !muscl_state(m, cell(I + 1, j), R, L, Rf)) {
 #pragma omp critical
           bad = (bad < 0 || c->ci(I, j) < bad) ? c->ci(I, j) : bad;
-          roe(m, L, R, F.nx, F.ny, F.F);
+          roe(m, L, R, F.nx, F.ny, eta_i(I, j), F.F);
         } else {
-          roe(m, Lf, Rf, F.nx, F.ny, F.F);
+          roe(m, Lf, Rf, F.nx, F.ny, eta_i(I, j), F.F);
         }
       } else {
-        roe(m, L, R, F.nx, F.ny, F.F);
+        roe(m, L, R, F.nx, F.ny, eta_i(I, j), F.F);
       }
     } else {
       hlle(m, L, R, F.nx, F.ny, F.F);
@@ -799,12 +835,12 @@ int orc_residual(orc_ctx *c, double cfl, double *norms) {
         if (!muscl_state(m, cell(i, J - 2), L, R, Lf) || !muscl_state(m, cell(i, J + 1), R, L, Rf)) {
 #pragma omp critical
           bad = (bad < 0 || c->ci(i, J) < bad) ? c->ci(i, J) : bad;
-          roe(m, L, R, F.nx, F.ny, F.F);
+          roe(m, L, R, F.nx, F.ny, eta_j(i, J), F.F);
         } else {
-          roe(m, Lf, Rf, F.nx, F.ny, F.F);
+          roe(m, Lf, Rf, F.nx, F.ny, eta_j(i, J), F.F);
         }
       } else {
-        roe(m, L, R, F.nx, F.ny, F.F);
+        roe(m, L, R, F.nx, F.ny, eta_j(i, J), F.F);
       }
     } else {
       hlle(m, L, R, F.nx, F.ny, F.F);
@@ -1454,11 +1490,11 @@ int orc_point_hlle(orc_ctx *c, const double *qL, const double *qR, double nx, do
   return 0;
 }
 
-int orc_point_roe(orc_ctx *c, const double *qL, const double *qR, double nx, double ny, double *F) {
-  if (!c || !c->has_mech) return -1;
+int orc_point_roe(orc_ctx *c, const double *qL, const double *qR, double nx, double ny, double eta, double *F) {
+  if (!c || !c->has_mech || !(eta >= 0.0)) return -1;
   CellD L, R;
   if (!make_cell(c->m, qL, L) || !make_cell(c->m, qR, R)) return c->fail(-4, "non-physical point state");
-  roe(c->m, L, R, nx, ny, F);
+  roe(c->m, L, R, nx, ny, eta, F);
   return 0;
 }
 

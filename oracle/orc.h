@@ -115,8 +115,9 @@ int orc_point_flux_jacobian(orc_ctx *ctx, const double *q, double nx, double ny,
 int orc_point_flux(orc_ctx *ctx, const double *q, double nx, double ny, double *F);
 /* HLLE face flux between left state qL and right state qR, unit normal (nx, ny) from L to R */
 int orc_point_hlle(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double *F);
-/* Roe face flux (MUSCL + Roe residual scheme) between states qL and qR */
-int orc_point_roe(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double *F);
+/* Roe face flux (MUSCL + Roe residual scheme) between states qL and qR; eta
+ * >= 0: the H-correction's floor on the wave speeds (0 for none) */
+int orc_point_roe(orc_ctx *ctx, const double *qL, const double *qR, double nx, double ny, double eta, double *F);
 /* MUSCL (minmod) face state on the side of cell B: A beyond B, C across the face */
 int orc_point_muscl(orc_ctx *ctx, const double *qA, const double *qB, const double *qC, double *qf);
 /* off-diagonal neighbour term at state q: mode 0 coupled (x in z), 1 flow part

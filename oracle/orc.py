@@ -259,11 +259,12 @@ class Oracle:
         self._check(self.L.orc_point_hlle(self.ctx, pl, pr, C.c_double(nx), C.c_double(ny), F.ctypes.data_as(_dp)))
         return F
 
-    def point_roe(self, qL, qR, nx, ny):
+    def point_roe(self, qL, qR, nx, ny, eta=0.0):
         F = np.zeros(self.mech.nv)
         a, pl = _d(qL)
         b, pr = _d(qR)
-        self._check(self.L.orc_point_roe(self.ctx, pl, pr, C.c_double(nx), C.c_double(ny), F.ctypes.data_as(_dp)))
+        self._check(self.L.orc_point_roe(self.ctx, pl, pr, C.c_double(nx), C.c_double(ny), C.c_double(eta),
+                                         F.ctypes.data_as(_dp)))
         return F
 
     def point_muscl(self, qA, qB, qC):

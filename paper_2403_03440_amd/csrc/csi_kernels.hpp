@@ -208,10 +208,11 @@ __device__ __forceinline__ bool roe_state_muscl(const Mech &m, const double *pri
 // gas of fixed composition); the waves at u.n carry the rest of the rho E
 // jump, a2 e2 = d(rho E) - H dp / c^2 - rho V.dV, which keeps Roe's property
 // for a real-gas mixture (e2 = H - c^2 / beta for a perfect gas); Harten's
-// entropy fix (delta = c / 10) on the acoustic waves
+// entropy fix (delta = c / 10) on the acoustic waves; eta: the H-correction's
+// floor on every wave speed
 template <int NS, int NT>
 __device__ __forceinline__ void roe_flux(const RoeState<NS> &L, const RoeState<NS> &R, double nx, double ny,
-                                         double *F) {
+                                         double eta, double *F) {
   const double unL = L.u * nx + L.v * ny, unR = R.u * nx + R.v * ny;
   const double sL = sqrt(L.rho), sR = sqrt(R.rho), w = sL / (sL + sR), wr = 1.0 - w;
   const double u = w * L.u + wr * R.u, v = w * L.v + wr * R.v, H = w * L.H + wr * R.H;
@@ -231,7 +232,7 @@ __device__ __forceinline__ void roe_flux(const RoeState<NS> &L, const RoeState<N
     const double a = fabs(l);
     return a < delta ? (l * l + delta * delta) / (2.0 * delta) : a;
   };
-  const double l1 = fix(un - c), l2 = fabs(un), l3 = fix(un + c);
+  const double l1 = fmax(fix(un - c), eta), l2 = fmax(fabs(un), eta), l3 = fmax(fix(un + c), eta);
   const double a2e2 = (R.rE - L.rE) - H * dp / c2 - rho * (u * dVx + v * dVy);
   const double D0 = l1 * a1 + l2 * a2 + l3 * a3;
   const double Dx = l1 * a1 * (u - c * nx) + l2 * (a2 * u - at * ny) + l3 * a3 * (u + c * nx);
@@ -248,12 +249,50 @@ __device__ __forceinline__ void roe_flux(const RoeState<NS> &L, const RoeState<N
   if (NT == 2) F[NS + 3] = fm * U.eve;
 }
 
+// The H-correction of Sanders, Morano and Druguet against the carbuncle of
+// Roe's flux at a shock aligned with the grid: eta of a face is half the
+// largest jump of a characteristic speed across it, (|un_R - un_L| +
+// |c_R - c_L|) / 2 from the two cells' states, and a face's wave speeds are
+// floored by the largest eta among itself and the four faces of the other
+// family that share an edge with it.
+__device__ __forceinline__ double eta_cells(const double *prim, size_t NP, int pL, int pR, double nx, double ny) {
+  const double unL = prim[F_U * NP + pL] * nx + prim[F_V * NP + pL] * ny;
+  const double unR = prim[F_U * NP + pR] * nx + prim[F_V * NP + pR] * ny;
+  return 0.5 * (fabs(unR - unL) + fabs(prim[F_C * NP + pR] - prim[F_C * NP + pL]));
+}
+
+__device__ __forceinline__ double eta_iface(const Geo &g, const double *prim, int I, int j) {
+  const size_t NP = g.NP;
+  const int f = j * (g.ni + 1) + I;
+  double e = eta_cells(prim, NP, padc(g, I - 1, j), padc(g, I, j), g.fi_nx[f], g.fi_ny[f]);
+  for (int i = I - 1; i <= I; ++i) {
+    if (i < 0 || i >= g.ni) continue;
+    for (int J = j; J <= j + 1; ++J)
+      e = fmax(e, eta_cells(prim, NP, padc(g, i, J - 1), padc(g, i, J), g.fj_nx[J * g.ni + i], g.fj_ny[J * g.ni + i]));
+  }
+  return e;
+}
+
+__device__ __forceinline__ double eta_jface(const Geo &g, const double *prim, int i, int J) {
+  const size_t NP = g.NP;
+  const int f = J * g.ni + i;
+  double e = eta_cells(prim, NP, padc(g, i, J - 1), padc(g, i, J), g.fj_nx[f], g.fj_ny[f]);
+  for (int j = J - 1; j <= J; ++j) {
+    if (j < 0 || j >= g.nj) continue;
+    for (int I = i; I <= i + 1; ++I) {
+      const int fi = j * (g.ni + 1) + I;
+      e = fmax(e, eta_cells(prim, NP, padc(g, I - 1, j), padc(g, I, j), g.fi_nx[fi], g.fi_ny[fi]));
+    }
+  }
+  return e;
+}
+
 // the inviscid face flux of the MUSCL + Roe scheme; pLL / pRR: the cells
 // beyond pL / pR (used at interior faces); false on a non-physical
 // reconstructed state (the flux is then the first-order Roe flux)
 template <int NS, int NT>
 __device__ __forceinline__ bool muscl_roe_flux(const Mech &m, const double *prim, size_t NP, int pLL, int pL, int pR,
-                                               int pRR, bool interior, double nx, double ny, double *F) {
+                                               int pRR, bool interior, double nx, double ny, double eta, double *F) {
   RoeState<NS> L, R;
   bool ok = true;
   if (interior)
@@ -262,7 +301,7 @@ __device__ __forceinline__ bool muscl_roe_flux(const Mech &m, const double *prim
     roe_state_cell<NS>(prim, NP, pL, L);
     roe_state_cell<NS>(prim, NP, pR, R);
   }
-  roe_flux<NS, NT>(L, R, nx, ny, F);
+  roe_flux<NS, NT>(L, R, nx, ny, eta, F);
   return ok;
 }
 
@@ -391,7 +430,8 @@ __global__ void __launch_bounds__(256) k_face_i(Geo g, const Mech *__restrict__ 
   bool interior = I > 0 && I < g.ni;
   if constexpr (SCH == 1) {
     if (!muscl_roe_flux<NS, NT>(*mech, prim, NP, interior ? padc(g, I - 2, j) : pL, pL, pR,
-                                interior ? padc(g, I + 1, j) : pR, interior, nx, ny, F) && bad)
+                                interior ? padc(g, I + 1, j) : pR, interior, nx, ny, eta_iface(g, prim, I, j), F) &&
+        bad)
       atomicMin(bad, j * g.ni + (I < g.ni ? I : g.ni - 1));
   } else {
     hlle_flux<NS, NT>(L, R, nx, ny, F);
@@ -436,7 +476,8 @@ __global__ void __launch_bounds__(256) k_face_j(Geo g, const Mech *__restrict__ 
   bool interior = J > 0 && J < g.nj;
   if constexpr (SCH == 1) {
     if (!muscl_roe_flux<NS, NT>(m, prim, NP, interior ? padc(g, i, J - 2) : pL, pL, pR,
-                                interior ? padc(g, i, J + 1) : pR, interior, nx, ny, F) && bad)
+                                interior ? padc(g, i, J + 1) : pR, interior, nx, ny, eta_jface(g, prim, i, J), F) &&
+        bad)
       atomicMin(bad, (J < g.nj ? J : g.nj - 1) * g.ni + i);
   } else {
     hlle_flux<NS, NT>(L, R, nx, ny, F);

@@ -11,6 +11,11 @@ paper's cylinder case, Section 3.2, built as the residual ablation).
   strength, average or sign breaks one of these, and so does the perfect-gas
   contact energy H - c^2 / beta used for a real gas (an 8 % energy-flux error
   across a hypersonic shock).
+* H-correction (the carbuncle cure): a floor eta above every wave speed
+  turns the Roe flux into the local Lax-Friedrichs flux with speed eta, the
+  species carried by that flux's mass flux; a floor below every wave speed
+  changes nothing.  The residual of a state mirrored about the stagnation
+  line is mirrored (a neighbour face taken from the wrong side breaks it).
 * MUSCL with minmod: linear data reconstruct to the face midpoint, an
   extremum falls back to the cell value, and minmod takes the smaller of two
   same-signed slopes.
@@ -184,3 +189,47 @@ def test_muscl_roe_residual():
     o.set_state(q1)
     o.residual(5.0)
     assert np.abs(R2 - o.get("R")).max() > 1e-3 * np.abs(R2).max()
+
+
+def test_h_correction_limits():
+    m = I.air5(1)
+    o = _oracle(m)
+    n = np.array([0.6, 0.8])
+    qL = _q(o, m, [1e-4, 2e-4, 1e-5, 2e-3, 5e-3], 400.0, -200.0, 2500.0, 2000.0)
+    qR = _q(o, m, [3e-4, 1e-4, 2e-5, 1e-3, 6e-3], -100.0, 300.0, 3500.0, 3900.0)
+    FL, FR = o.point_flux(qL, *n), o.point_flux(qR, *n)
+    eta = 1e4  # above |u.n| + c of both states and of their average
+    F = o.point_roe(qL, qR, *n, eta=eta)
+    ns = m.ns
+    lf = 0.5 * (FL + FR) - 0.5 * eta * (qR - qL)
+    fm = lf[:ns].sum()
+    assert _rel(F[ns:ns + 3], lf[ns:ns + 3]) <= 1e-13
+    assert abs(F[:ns].sum() - fm) <= 1e-13 * abs(fm) + 1e-13 * np.abs(lf[:ns]).max()
+    up = qL if fm >= 0.0 else qR
+    assert np.allclose(F[:ns], fm * up[:ns] / up[:ns].sum(), rtol=1e-13, atol=0.0)
+    # a floor below every wave speed: no change
+    assert np.array_equal(o.point_roe(qL, qR, *n, eta=1.0), o.point_roe(qL, qR, *n))
+
+
+def test_muscl_roe_residual_mirror_symmetry():
+    m = I.air5(1)
+    ni, nj = 12, 8
+    x, y = I.polar_grid(ni, nj)
+    fs = (np.array([0.0, 0.0, 0.0, 0.233e-3, 0.767e-3]), 3000.0, 0.0, 300.0, 300.0)
+    o = orc.setup((x, y), m, fs)
+    o.set_option("residual_scheme", 1)
+    rs, u, v, T, Tv = I.random_prims(m, ni * nj, 9, T_range=(400.0, 3000.0), speed=800.0, y_floor=0.02)
+    # mirror about the stagnation line: cell (i, j) <-> (ni - 1 - i, j), v -> -v
+    idx = np.arange(ni * nj).reshape(nj, ni)
+    mir = idx[:, ::-1].ravel()
+    half = (idx % ni < ni // 2).ravel()
+    rs, u, v, T, Tv = (np.where(half, a, a[..., mir]) for a in (rs, u, v, T, Tv))
+    v = np.where(half, v, -v[mir])
+    assert np.allclose(y[:, ::-1], -y) and np.allclose(x[:, ::-1], x)
+    o.set_state(o.prim_to_cons(rs, u, v, T, Tv))
+    o.residual(5.0)
+    R = o.get("R")
+    Rm = R[:, mir].copy()
+    Rm[m.ns + 1] *= -1.0
+    scale = np.abs(R).max(axis=1, keepdims=True)
+    assert np.all(np.abs(R - Rm) <= 1e-11 * scale)
