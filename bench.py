@@ -317,6 +317,62 @@ def scaling(csi, I, ns_list, steps, warmup, n_side=16):
             "rows": rows, "fitted_exponent_implicit": fit}
 
 
+def residual_ablation(csi, I, config, speeds, max_iter, tol, chunk=2000):
+    """The residual scheme as an ablation (the MUSCL (minmod) + Roe residual
+    of the paper's cylinder case, Section 3.2, against the default
+    first-order HLLE): on the config's grid, mechanism and CFL schedule with
+    the free-stream speed replaced, each form (split mixed CC2, coupled FP64)
+    from the free stream until the density residual has dropped by tol or
+    max_iter iterations have run, checked every chunk iterations.  Per run:
+    iterations, seconds (with HIP events per phase on), the drop after each
+    chunk, the error that stopped it, if any (a non-physical state), and
+    the mean time per iteration of each phase."""
+    import torch
+    base = I.CONFIGS[config]
+    runs = []
+    for u in speeds:
+        cfg = dataclasses.replace(base, u_inf=u)
+        m = cfg.mechanism()
+        x, y = cfg.grid()
+        fs = I.freestream_prims(cfg, m)
+        for scheme, sname in ((1, "muscl_roe"), (0, "hlle")):
+            for form, mode, kind, prec in (("split mixed", 1, 2, csi.MIXED), ("coupled FP64", 0, 0, csi.FP64)):
+                s = csi.Solver((x, y), m, fs)
+                s.set_residual_scheme(scheme)
+                s.set_state(s.initial_state(*I.initial_prims(cfg, m)))
+                s.set_timing(True)
+                run = {"u_inf": u, "residual": sname, "form": form, "drops": [], "error": None}
+                done, r0 = 0, None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                try:
+                    while done < max_iter:
+                        st = s.step(mode, kind, cfg.cfl, min(chunk, max_iter - done), precision=prec,
+                                    cfl_ramp=cfg.ramp if done == 0 else 0, check_every=100)
+                        r0 = st["r0"] if r0 is None else r0
+                        done += st["iters"]
+                        run["drops"].append([done, st["r_last"] / r0])
+                        if st["r_last"] / r0 <= tol:
+                            break
+                except csi.CsiError as e:
+                    run["error"] = str(e)
+                torch.cuda.synchronize()
+                run["iters"] = done
+                run["seconds"] = time.perf_counter() - t0
+                run["phases_ms_per_iter"] = {k: p["ms_per_iter"] for k, p in s.phase_times().items()
+                                             if isinstance(p, dict)}
+                print(f"# {sname} u {u:.0f} {form}: {done} it, drop {run['drops'][-1][1] if run['drops'] else None}, "
+                      f"{run['seconds']:.1f} s{', ' + run['error'] if run['error'] else ''}", file=sys.stderr,
+                      flush=True)
+                runs.append(run)
+                del s
+                torch.cuda.empty_cache()
+    return {"metric": "residual-scheme ablation: density-residual drop against iterations", "unit": "drop",
+            "config": {"workload": f"{config} grid, mechanism and CFL schedule with the free-stream speed replaced; "
+                                   f"to a {tol:g} drop or {max_iter} iterations"},
+            "runs": runs}
+
+
 def oracle_threads():
     n = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS")
@@ -474,6 +530,8 @@ def main():
                                                  "study (implicit iteration time of CI and CS in non-reacting flow) "
                                                  "instead of the workload above")
     ap.add_argument("--scaling-grid", type=int, default=16, help="cells per side of the species-count study's box")
+    ap.add_argument("--residual-ablation", default="", help="free-stream speeds (e.g. 2000,5000): MUSCL + Roe "
+                    "against HLLE, both forms, on --config (default c2 for this study) to --tol or --max-iter")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this implementation runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -486,6 +544,11 @@ def main():
     if args.scaling:
         print(json.dumps(scaling(csi, I, [int(v) for v in args.scaling.split(",")], args.steps, args.warmup,
                                  args.scaling_grid)))
+        return
+    if args.residual_ablation:
+        config = args.config if args.config != "c5" else "c2"
+        print(json.dumps(residual_ablation(csi, I, config, [float(v) for v in args.residual_ablation.split(",")],
+                                           args.max_iter, args.tol)))
         return
     cfg = I.CONFIGS[args.config]
     if args.ramp:
