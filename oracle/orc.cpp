@@ -1219,15 +1219,13 @@ int sweeps(orc_ctx *c, int mode, int order, const std::vector<double> &b) {
   return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-int orc_implicit_op(orc_ctx *c, int mode, int order) {
-  if (!c || !c->has_res) return c ? c->fail(-3, "residual not computed") : -1;
+// the sweeps' right-hand side from the residual: -R in the coupled form's z
+// variables, or the flow part (total density, momenta, energies) and the
+// species part of the split form
+void sweep_rhs_from_residual(orc_ctx *c, int mode, std::vector<double> &b) {
   const Mech &m = c->m;
   const int N = c->N, ns = m.ns, nf = m.nf(), nsol = nsol_of(m, mode);
-  std::vector<double> b(size_t(nsol) * N);
+  b.assign(size_t(nsol) * N, 0.0);
   for (int p = 0; p < N; ++p) {
     double rq[MAXV], rz[MAXV];
     for (int k = 0; k < m.nv(); ++k) rq[k] = c->R[size_t(k) * N + p];
@@ -1245,7 +1243,37 @@ int orc_implicit_op(orc_ctx *c, int mode, int order) {
       for (int s = 0; s < ns; ++s) b[size_t(nf + s) * N + p] = -rq[s];
     }
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_implicit_op(orc_ctx *c, int mode, int order) {
+  if (!c || !c->has_res) return c ? c->fail(-3, "residual not computed") : -1;
+  std::vector<double> b;
+  sweep_rhs_from_residual(c, mode, b);
   return sweeps(c, mode, order, b);
+}
+
+int orc_sweep_cell(orc_ctx *c, int mode, int fwd, int i, int j, const double *xs, const double *x, double *out) {
+  if (!c || !c->has_res || !xs || !out || (!fwd && !x)) return c ? c->fail(-1, "sweep_cell: arguments") : -1;
+  if (i < 0 || i >= c->ni || j < 0 || j >= c->nj) return c->fail(-1, "sweep_cell: cell out of range");
+  const int N = c->N, nsol = nsol_of(c->m, mode);
+  std::vector<double> b, xsv(xs, xs + size_t(nsol) * N), xv;
+  if (fwd) sweep_rhs_from_residual(c, mode, b);
+  else xv.assign(x, x + size_t(nsol) * N);
+  const Part parts[2] = {mode == ORC_COUPLED ? P_COUPLED : P_FLOW, P_SPECIES};
+  c->fd_bad = -1;
+  for (int q = 0; q < (mode == ORC_COUPLED ? 1 : 2); ++q) {
+    const PartInfo pi = part_info(c, parts[q], mode);
+    if (fwd) sweep_cell_fwd(c, parts[q], pi, i, j, b, xsv);
+    else sweep_cell_bwd(c, parts[q], pi, i, j, xsv, xv);
+  }
+  const int p = c->ci(i, j);
+  const std::vector<double> &res = fwd ? xsv : xv;
+  for (int k = 0; k < nsol; ++k) out[k] = res[size_t(k) * N + p];
+  return c->fd_bad >= 0 ? c->fail(-4, "flux difference at a non-physical neighbour state") : 0;
 }
 
 int orc_sweep_rhs(orc_ctx *c, int mode, int order, const double *b, double *x) {

@@ -86,7 +86,14 @@ int orc_get_state(orc_ctx *ctx, double *q);
 int orc_residual(orc_ctx *ctx, double cfl, double *norms);
 /* LU-SGS forward+backward sweeps with b = -R (mode coupled/split, order hyperplane/lexicographic) */
 int orc_implicit_op(orc_ctx *ctx, int mode, int order);
-/* same sweeps with a caller RHS b [nsol][N]; result x [nsol][N] */
+/* One cell (i, j) of the sweeps of the last residual's operator, every other
+ * cell's values given ([nsol][N] arrays): fwd = 1 solves the cell's row of
+ * (D+L) dQ* = b (b formed from the residual as orc_implicit_op forms it) with
+ * the lower neighbours' dQ* from xs; fwd = 0 the row of (D+U) dQ = D dQ* with
+ * the upper neighbours' dQ from x and the cell's dQ* from xs.  out [nsol].
+ * For checks of a full-size run at sampled cells (on a patch of the grid). */
+int orc_sweep_cell(orc_ctx *ctx, int mode, int fwd, int i, int j, const double *xs, const double *x, double *out);
+/* the sweeps of orc_implicit_op with a caller RHS b [nsol][N]; result x [nsol][N] */
 int orc_sweep_rhs(orc_ctx *ctx, int mode, int order, const double *b, double *x);
 /* closure (coupled) or CC1/CC2 (split) and the update of q */
 int orc_consistency_correct(orc_ctx *ctx, int mode, int kind, int *n_clipped);

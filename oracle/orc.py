@@ -189,6 +189,17 @@ class Oracle:
         self._check(self.L.orc_consistency_correct(self.ctx, mode, kind, C.byref(n)))
         return n.value
 
+    def sweep_cell(self, mode, fwd, i, j, xs, x=None):
+        """One cell of the sweeps with the other cells' values given (see orc.h)."""
+        out = np.zeros(self.nsol(mode))
+        a, pxs = _d(xs)
+        if x is not None:
+            b_, px = _d(x)
+        else:
+            px = None
+        self._check(self.L.orc_sweep_cell(self.ctx, mode, int(fwd), i, j, pxs, px, out.ctypes.data_as(_dp)))
+        return out
+
     def step(self, mode, kind, cfl, n_iter, ramp=0, it0=0):
         h = np.zeros((n_iter, 2))
         self._check(self.L.orc_step(self.ctx, mode, kind, C.c_double(cfl), ramp, it0, n_iter,

@@ -9,9 +9,13 @@ its four faces and their nodes, so the oracle computes them on a 5 x 5 patch
 of the full grid (nodes and states copied) around the sampled cell (for
 cells next to the wall the patch's bottom row is the wall row).  Checked per
 sampled cell: R per stored variable to 1e-11 of the samples' largest
-magnitude in its variable group, and D^-1 (coupled block; split flow and
+magnitude in its variable group; D^-1 (coupled block; split flow and
 species blocks) against the inverse of the oracle's block to
-max(1e-11, 1e-13 cond(D)) in the Frobenius norm."""
+max(1e-11, 1e-13 cond(D)) in the Frobenius norm; and the sweeps: the cell's
+dQ* against the oracle's row of (D+L) dQ* = b, and its dQ against the row of
+(D+U) dQ = D dQ*, each solved with the neighbours' values taken from the
+GPU's own run (orc_sweep_cell on the patch), per unknown to
+max(1e-11, 1e-13 cond(D)) of the samples' largest magnitude in its group."""
 import numpy as np
 import pytest
 
@@ -40,7 +44,7 @@ def _patch(cfg, m, x, y, fs, q, i, j):
     cells = [(jj * cfg.ni + ii) for jj in range(j0, j0 + P) for ii in range(i0, i0 + P)]
     o = orc.setup((xp, yp), m, fs, T_wall=cfg.T_wall)
     o.set_state(np.ascontiguousarray(q[:, cells]))
-    return o, (j - j0) * P + (i - i0)
+    return o, (j - j0) * P + (i - i0), cells
 
 
 def _dinv_err(Dg, Do):
@@ -67,7 +71,7 @@ def test_full_size_sampled_cells(name):
     Rg = s.get_cells("R", cells)
     patches = [_patch(cfg, m, x, y, fs, q, i, j) for i, j in ij]
     Ro = np.zeros_like(Rg)
-    for k, (o, c) in enumerate(patches):
+    for k, (o, c, _) in enumerate(patches):
         o.residual(cfl)
         Ro[:, k] = o.get("R")[:, c]
     scale = np.abs(Ro).max(axis=1)
@@ -81,7 +85,8 @@ def test_full_size_sampled_cells(name):
         s.implicit_op(mode, csi.FP64)
         Dg = s.get_cells("Dinv", cells, mode)
         worst = 0.0
-        for k, (o, c) in enumerate(patches):
+        conds = []
+        for k, (o, c, _) in enumerate(patches):
             o.residual(cfl)
             o.implicit_op(mode)
             if mode == csi.COUPLED:
@@ -90,8 +95,34 @@ def test_full_size_sampled_cells(name):
                 nf2 = m.nf * m.nf
                 blocks = [(Dg[:nf2, k].reshape(m.nf, m.nf), o.get("DF", mode)[:, :, c]),
                           (Dg[nf2:, k].reshape(m.ns, m.ns), o.get("DC", mode)[:, :, c])]
+            cmax = 0.0
             for Dgk, Dok in blocks:
                 e, cond = _dinv_err(Dgk, Dok)
+                cmax = max(cmax, cond)
                 worst = max(worst, e / max(1e-11, 1e-13 * cond))
                 assert e <= max(1e-11, 1e-13 * cond), (ij[k], e, cond)
+            conds.append(cmax)
         print(f"mode {mode}: D^-1 worst error / tolerance {worst:.2e}", flush=True)
+        # the sweeps, one row per sampled cell with the GPU's neighbour values
+        allc = [cl for _, _, pc in patches for cl in pc]
+        xs_all = s.get_cells("dqs", allc, mode)
+        x_all = s.get_cells("dq", allc, mode)
+        nc = P * P
+        fwd, bwd, gf, gb = [], [], [], []
+        for k, (o, c, _) in enumerate(patches):
+            xs = xs_all[:, k * nc:(k + 1) * nc]
+            xg = x_all[:, k * nc:(k + 1) * nc]
+            fwd.append(o.sweep_cell(mode, 1, c % P, c // P, xs))
+            bwd.append(o.sweep_cell(mode, 0, c % P, c // P, xs, xg))
+            gf.append(xs[:, c])
+            gb.append(xg[:, c])
+        from gpu_cases import groups_inc
+        for name_, go, oo in (("dQ*", gf, fwd), ("dQ", gb, bwd)):
+            go, oo = np.array(go).T, np.array(oo).T
+            sc = np.abs(oo).max(axis=1)
+            for g in groups_inc(m, mode):
+                sc[g] = sc[g].max()
+            err = np.abs(go - oo) / sc[:, None]
+            tol = np.maximum(1e-11, 1e-13 * np.array(conds))[None, :]
+            print(f"mode {mode}: {name_} rows worst error / tolerance {(err / tol).max():.2e}", flush=True)
+            assert np.all(err <= tol), (name_, (err / tol).max())

@@ -503,3 +503,23 @@ def test_zero_residual_gives_zero_increment():
         mom = np.hypot(qs[m.ns], qs[m.ns + 1]).max()
         scale = np.r_[qs[:m.ns].sum(0).max(), mom, mom, np.abs(qs[m.ns + 2]).max()]
         assert np.all(np.abs(dq[:4]).max(1) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("mode", [orc.COUPLED, orc.SPLIT])
+def test_sweep_cell_reproduces_the_sweeps(mode):
+    """orc_sweep_cell (one cell's row of each sweep, the other cells' values
+    given) returns the full sweeps' own values at every cell, bitwise: the
+    sampled-cell checks of full-size runs rest on it."""
+    m = I.air5(1)
+    x, y = I.polar_grid(7, 5)
+    fs = (np.array([0.0, 0.0, 0.0, 0.233e-3, 0.767e-3]), 3000.0, 0.0, 250.0, 250.0)
+    o = orc.setup((x, y), m, fs)
+    prims = I.random_prims(m, 35, 4, T_range=(400.0, 3000.0), speed=600.0, y_floor=0.02)
+    o.set_state(o.prim_to_cons(*prims))
+    o.residual(20.0)
+    o.implicit_op(mode)
+    dqs, dq = o.get("dqs", mode), o.get("dq", mode)
+    for p in range(35):
+        i, j = p % 7, p // 7
+        assert np.array_equal(o.sweep_cell(mode, 1, i, j, dqs), dqs[:, p])
+        assert np.array_equal(o.sweep_cell(mode, 0, i, j, dqs, dq), dq[:, p])
