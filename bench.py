@@ -122,6 +122,7 @@ def measured_traffic(kernel, workload):
 
 
 JC_READING = -1  # split species block reading (csi_set_species_jacobian); -1 keeps the default
+RESIDUAL_SCHEME = 0  # csi_set_residual_scheme: 0 first-order HLLE, 1 MUSCL + Roe
 
 
 def new_solver(csi, I, cfg, m, x, y, fs, sur=None):
@@ -129,6 +130,8 @@ def new_solver(csi, I, cfg, m, x, y, fs, sur=None):
     s.set_state(s.initial_state(*I.initial_prims(cfg, m)))
     if JC_READING >= 0:
         s.set_species_jacobian(JC_READING)
+    if RESIDUAL_SCHEME:
+        s.set_residual_scheme(RESIDUAL_SCHEME)
     if sur is not None:
         s.set_surrogate(sur["params"], sur["scales"])
     return s
@@ -357,11 +360,12 @@ def residual_ablation(csi, I, config, speeds, max_iter, tol, chunk=2000):
                 except csi.CsiError as e:
                     run["error"] = str(e)
                 torch.cuda.synchronize()
-                run["iters"] = done
+                ph = s.phase_times()
+                # iterations run, the one that failed included (the timing counts every iteration)
+                run["iters"] = max(done, int(ph["iters"]))
                 run["seconds"] = time.perf_counter() - t0
-                run["phases_ms_per_iter"] = {k: p["ms_per_iter"] for k, p in s.phase_times().items()
-                                             if isinstance(p, dict)}
-                print(f"# {sname} u {u:.0f} {form}: {done} it, drop {run['drops'][-1][1] if run['drops'] else None}, "
+                run["phases_ms_per_iter"] = {k: p["ms_per_iter"] for k, p in ph.items() if isinstance(p, dict)}
+                print(f"# {sname} u {u:.0f} {form}: {run['iters']} it, drop {run['drops'][-1][1] if run['drops'] else None}, "
                       f"{run['seconds']:.1f} s{', ' + run['error'] if run['error'] else ''}", file=sys.stderr,
                       flush=True)
                 runs.append(run)
@@ -530,6 +534,8 @@ def main():
                                                  "study (implicit iteration time of CI and CS in non-reacting flow) "
                                                  "instead of the workload above")
     ap.add_argument("--scaling-grid", type=int, default=16, help="cells per side of the species-count study's box")
+    ap.add_argument("--residual", choices=("hlle", "muscl"), default="hlle",
+                    help="residual scheme of the throughput and time-to-tolerance legs")
     ap.add_argument("--residual-ablation", default="", help="free-stream speeds (e.g. 2000,5000): MUSCL + Roe "
                     "against HLLE, both forms, on --config (default c2 for this study) to --tol or --max-iter")
     args = ap.parse_args()
@@ -563,8 +569,9 @@ def main():
     names = [v for v in args.variants.split(",") if v]
     if HEADLINE not in names:
         names.insert(0, HEADLINE)
-    global JC_READING
+    global JC_READING, RESIDUAL_SCHEME
     JC_READING = args.species_jacobian
+    RESIDUAL_SCHEME = {"hlle": 0, "muscl": 1}[args.residual]
     sur, sur_info = None, None
     if any(VARIANTS[v][3] for v in names):
         print("# surrogate: sampling and training", file=sys.stderr, flush=True)
@@ -595,7 +602,8 @@ def main():
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": workload_text(cfg, m) + ", headline: split solver, FP32 sweeps and block "
                                "inverses + FP64 residual/chemistry/CC2, species Jacobian block from the BF16 "
-                               "surrogate network with exact fallback",
+                               "surrogate network with exact fallback"
+                               + (", MUSCL (minmod) + Roe residual" if RESIDUAL_SCHEME else ""),
                    "cells": N},
         "roofline": roof,
         "whole_iteration_hbm": whole,
