@@ -11,7 +11,8 @@ cells next to the wall the patch's bottom row is the wall row).  Checked per
 sampled cell: R per stored variable to 1e-11 of the samples' largest
 magnitude in its variable group; D^-1 (coupled block; split flow and
 species blocks) against the inverse of the oracle's block to
-max(1e-11, 1e-13 cond(D)) in the Frobenius norm; and the sweeps: the cell's
+max(1e-11, 1e-13 cond(D)) in the Frobenius norm; R of the MUSCL + Roe
+residual of the same state to the same bar as R; and the sweeps: the cell's
 dQ* against the oracle's row of (D+L) dQ* = b, and its dQ against the row of
 (D+U) dQ = D dQ*, each solved with the neighbours' values taken from the
 GPU's own run (orc_sweep_cell on the patch), per unknown to
@@ -80,6 +81,25 @@ def test_full_size_sampled_cells(name):
     eR = (np.abs(Rg - Ro).max(axis=1) / scale).max()
     print(f"R: max error {eR:.2e} over {len(cells)} cells", flush=True)
     assert eR <= 1e-11
+    # the MUSCL + Roe residual of the same state (its stencil, two cells
+    # each side and the H-correction's transverse faces, lies in the patch)
+    s.set_residual_scheme(1)
+    s.residual(cfl)
+    Rg1 = s.get_cells("R", cells)
+    Ro1 = np.zeros_like(Rg1)
+    for k, (o, c, _) in enumerate(patches):
+        o.set_option("residual_scheme", 1)
+        o.residual(cfl)
+        Ro1[:, k] = o.get("R")[:, c]
+        o.set_option("residual_scheme", 0)
+    s.set_residual_scheme(0)
+    sc1 = np.abs(Ro1).max(axis=1)
+    for g in groups_state(m):
+        sc1[g] = sc1[g].max()
+    eR1 = (np.abs(Rg1 - Ro1).max(axis=1) / sc1).max()
+    print(f"R (MUSCL + Roe): max error {eR1:.2e} over {len(cells)} cells", flush=True)
+    assert eR1 <= 1e-11
+    assert np.abs(Ro1 - Ro).max() > 1e-6 * np.abs(Ro).max()
     for mode in (csi.SPLIT, csi.COUPLED):
         s.residual(cfl)
         s.implicit_op(mode, csi.FP64)
