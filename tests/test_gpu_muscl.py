@@ -11,8 +11,9 @@ case (Section 3.2), built as a residual ablation.
 * Iterations: 30 ramped steps of each form at 2 km/s from the free stream
   give the same norm history and state as the oracle's.  At that speed the
   Roe flux on this grid has no carbuncle.
-* Degenerate grids (one row, one column, two cells across): interior faces
-  next to a boundary reconstruct from the ghost cell.
+* Degenerate grids (one row, one column, two cells across) and the
+  far-field box: interior faces next to a boundary reconstruct from the
+  ghost cell.
 * Argument errors: an unknown scheme gives CSI_ERR_ARG; scheme 1 on the
   species-generic kernels gives CSI_ERR_UNSUPPORTED."""
 import numpy as np
@@ -123,6 +124,23 @@ def test_muscl_edge_shapes(ni, nj):
     csi = _csi()
     print(f"shape {ni}x{nj}", flush=True)
     m, o, s, q0 = _muscl_pair("air5_2T", ni, nj, "random", seed=11)
+    s.residual(5.0)
+    o.residual(5.0)
+    assert np.all(normwise(s.get("R"), o.get("R"), groups_state(m)) <= 1e-11)
+    for mode in (0, 1):
+        g = groups_inc(m, mode)
+        noise = oracle_noise(o, q0, mode, 5.0, g)
+        s.residual(5.0)
+        s.implicit_op(mode, csi.FP64)
+        tol = np.maximum(TOL64, 10.0 * noise)
+        assert np.all(normwise(s.get("dq", mode), o.get("dq", mode), g) <= tol)
+
+
+def test_muscl_far_field_box():
+    """bc_mode 1 (free stream on all four sides): ghost cells on every side
+    enter the reconstruction and the H-correction."""
+    csi = _csi()
+    m, o, s, q0 = _muscl_pair("air5_1T", 9, 6, "random", seed=2, bc_mode=1)
     s.residual(5.0)
     o.residual(5.0)
     assert np.all(normwise(s.get("R"), o.get("R"), groups_state(m)) <= 1e-11)
