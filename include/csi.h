@@ -374,15 +374,22 @@ int csi_mlp_train_step(csi_ctx *ctx, const csi_mlp_batch *b, float *m, float *v,
 int csi_mlp_train_epoch(csi_ctx *ctx, const csi_mlp_batch *b, const int *order, int n_rows, float *m, float *v,
                         int step0, const csi_adam *h, double *loss);
 
-/* Training samples from the bound state: for cells 0..n-1 (n = min(N,
- * max_samples), returned in *n_written) the raw features x_raw [n][ns + 3] and
- * the exact J_C [n][ns * ns] (FP32) of the species block's reading
- * (csi_set_species_jacobian).  Overwrites the diagonal-block hand-off of the
- * last implicit operator (ns >= 5).  There is no seed argument: the call is
- * deterministic and takes every cell of the state (the training set is whole
- * snapshots of the solver's own iterates); the seeded draw happens in the
- * training, whose batch order comes from a seeded permutation of the rows. */
-int csi_sample_jacobians(csi_ctx *ctx, int max_samples, float *x_raw, float *jc, int *n_written);
+/* Training samples for the surrogate of the species block's source Jacobian
+ * J_C (the component operator of Section 2.3), taken from Jacobians the
+ * solver itself generates, from the bound state: n = min(N,
+ * max_samples) rows, returned in *n_written, of raw features x_raw [n][ns + 3]
+ * (ln T, ln Tv, ln rho, Y) and the exact J_C [n][ns * ns] (FP32) of the
+ * species block's reading (csi_set_species_jacobian); host-visible or device
+ * pointers the device can write.  n = N: row r is cell r (the seed is
+ * unused).  n < N: a seeded subset of distinct cells, row r being cell
+ * (b + r a) mod N with b = splitmix64(seed) mod N and a the first value
+ * coprime with N from 1 + splitmix64(seed + 1) mod (N - 1) upwards, wrapping
+ * within [1, N - 1] (splitmix64: one step of Vigna's SplitMix64).  Overwrites
+ * the diagonal-block hand-off of the last implicit operator (ns >= 5).
+ * Errors: CSI_ERR_ARG (max_samples < 1, null buffers), CSI_ERR_STATE (no
+ * state), CSI_ERR_UNSUPPORTED (species-generic kernels), CSI_ERR_NONFINITE. */
+int csi_sample_jacobians(csi_ctx *ctx, int max_samples, unsigned long long seed, float *x_raw, float *jc,
+                         int *n_written);
 /* Install a trained network for CSI_JAC_SURROGATE (split form only):
  * params [n_params] (device, copied into the workspace), scales (host,
  * [2 n_in + 1] as from csi_mlp_prepare), n_in = ns + 3, n_out = ns^2.  Per

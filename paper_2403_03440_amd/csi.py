@@ -288,14 +288,16 @@ class Solver:
         return out
 
     # ---------------------------------------------------------- surrogate
-    def sample_jacobians(self, x_raw, jc, max_samples=None):
+    def sample_jacobians(self, x_raw, jc, max_samples=None, seed=0):
         """Features [n][ns+3] and exact J_C [n][ns*ns] (float32 cuda tensors) of
-        cells 0..n-1 of the current state; returns n."""
+        every cell of the current state (n = N), or of a seeded subset of
+        n = max_samples distinct cells (see csi.h); returns n."""
         n = C.c_int(0)
         ms = self.N if max_samples is None else max_samples
-        self._check(self.L.csi_sample_jacobians(self.ctx, ms, C.c_void_p(x_raw.data_ptr()),
+        self._check(self.L.csi_sample_jacobians(self.ctx, ms, C.c_ulonglong(seed), C.c_void_p(x_raw.data_ptr()),
                                                 C.c_void_p(jc.data_ptr()), C.byref(n)))
         return n.value
+
 
     def set_physical_time(self, dt, theta=0.0):
         """Dual time stepping: physical step dt (0: steady) and theta (0 backward

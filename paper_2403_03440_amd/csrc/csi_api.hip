@@ -894,6 +894,40 @@ int csi_set_species_generic(csi_ctx *c, int on) {
 }
 
 namespace {
+
+// SplitMix64 (Steele, Lea and Flood's generator, as published by Vigna): one
+// step of the sequence from x
+unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+long long gcd_ll(long long a, long long b) {
+  while (b) {
+    const long long t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// the seeded subset of csi_sample_jacobians: row r -> cell (b + r a) mod N
+// with b = splitmix64(seed) mod N and a the first value coprime with N from
+// 1 + splitmix64(seed + 1) mod (N - 1) upwards (wrapping within [1, N - 1])
+SampleMap sample_map(unsigned long long seed, int N) {
+  if (N <= 1) return SampleMap{1, 0};
+  const long long n = N;
+  long long b = (long long)(splitmix64(seed) % (unsigned long long)n);
+  long long a = 1 + (long long)(splitmix64(seed + 1) % (unsigned long long)(n - 1));
+  while (gcd_ll(a, n) != 1) a = a % (n - 1) + 1;
+  return SampleMap{a, b};
+}
+
+}  // namespace
+
+namespace {
 // scratch of csi_block_inverse: row interchanges, pivot rows, singular flag
 void block_inverse_layout(int n, int count, size_t off[3], size_t *total) {
   off[0] = 0;
@@ -1385,13 +1419,15 @@ int csi_mlp_train_epoch(csi_ctx *c, const csi_mlp_batch *b, const int *order, in
   return CSI_OK;
 }
 
-int csi_sample_jacobians(csi_ctx *c, int max_samples, float *x_raw, float *jc, int *n_written) {
+int csi_sample_jacobians(csi_ctx *c, int max_samples, unsigned long long seed, float *x_raw, float *jc,
+                         int *n_written) {
   if (!c) return CSI_ERR_ARG;
   if (max_samples < 1 || !x_raw || !jc) return c->fail(CSI_ERR_ARG, "sample_jacobians: arguments");
   if (!ready(c)) return c->fail(CSI_ERR_STATE, "sample_jacobians: workspace/state not set");
   if (c->wide) return c->fail(CSI_ERR_UNSUPPORTED, "sample_jacobians: no reactions on the species-generic kernels");
   const int n = max_samples < c->N ? max_samples : c->N;
-  int rc = hip_check(c, c->run->sample(c->g, c->w, c->stream, n, x_raw, jc, c->jc_flag()), "sample launch");
+  const SampleMap sm = n < c->N ? sample_map(seed, c->N) : SampleMap{0, 0};
+  int rc = hip_check(c, c->run->sample(c->g, c->w, c->stream, n, x_raw, jc, c->jc_flag(), sm), "sample launch");
   if (rc) return rc;
   int fl[FL_N];
   if ((rc = read_flags(c, fl))) return rc;

@@ -40,6 +40,7 @@ struct BlockOut {
   int *bad;                    // first singular cell
   float *jc_out;               // non-null: write the species block's J_C [n_lim][ns][ns] (FP32) and stop
   long n_lim;                  // cells written with jc_out
+  SampleMap smap;              // with jc_out: row r of jc_out is cell smap(r)
   // one temperature, flags bit 0 (the cell kernel formed the residual in
   // this pass without the chemical source): R [nv][N] receives the source
   // -V omega_s of the species rows and the right-hand side's species rows
@@ -365,7 +366,8 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
   double *buf = sh[live ? grp : 0];
   const long cell = long(xcd_block(blockIdx.x, gridDim.x)) * C + grp;
   const bool real = live && cell < (out.jc_out ? out.n_lim : long(g.N));
-  const int p = int(real ? cell : 0);
+  // sample mode: output row `cell` holds grid cell smap(cell)
+  const int p = int(real ? (out.jc_out ? out.smap(cell, g.N) : cell) : 0);
   const int i = p % g.ni, j = p / g.ni;
   const int pc = padc(g, i, j);
   const size_t NP = g.NP;
@@ -589,7 +591,7 @@ __global__ void __launch_bounds__(64) k_block(Geo g, const Mech *__restrict__ me
     if (out.jc_out) {
       if (real && t >= 0)
 #pragma unroll
-        for (int c = 0; c < NS; ++c) out.jc_out[(size_t(p) * NS + t) * NS + c] = float(jr[c]);
+        for (int c = 0; c < NS; ++c) out.jc_out[(size_t(cell) * NS + t) * NS + c] = float(jr[c]);
       return;
     }
     // flow block: diagonal 1/dF, and in two temperatures the rho e_ve row

@@ -7,6 +7,13 @@
 
 namespace csi {
 
+// Cells of a training sample: row r holds cell (b + r a) mod n; a = 0: row r
+// is cell r.  a is coprime with n, so distinct rows are distinct cells.
+struct SampleMap {
+  long long a, b;
+  __host__ __device__ long operator()(long r, long n) const { return a ? long((b + (long long)r * a) % n) : r; }
+};
+
 // ------------------------------------------------------------ workspace view
 struct Geo {
   int ni, nj, N, NP, bc_mode;
@@ -690,10 +697,12 @@ __device__ __forceinline__ void write_handoff(const Mech &m, const double *rs, c
 // block kernel's species Jacobian)
 template <int NS, int NT>
 __global__ void __launch_bounds__(256) k_handoff(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
-                                                 const double *__restrict__ prim, int n, double *__restrict__ diag) {
+                                                 const double *__restrict__ prim, int n, double *__restrict__ diag,
+                                                 SampleMap sm) {
   constexpr int NV = Dims<NS, NT>::nv;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int p = int(sm(r, g.N));
   const Mech &m = *mech;
   const size_t NP = g.NP;
   const int pc = padc(g, p % g.ni, p / g.ni);

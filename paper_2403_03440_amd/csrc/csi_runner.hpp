@@ -61,7 +61,8 @@ class IRunner {
                            StallArgs stall = StallArgs{nullptr, 0, 0, 0.0}) = 0;
   virtual hipError_t surrogate(const Geo &g, const WS &w, hipStream_t st, bool stoppable) = 0;
   // flags bit 3: the species block's reading with the temperatures following the composition
-  virtual hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc, int flags) = 0;
+  virtual hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc, int flags,
+                            SampleMap sm) = 0;
   virtual hipError_t sweeps(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, bool stoppable,
                             hipEvent_t mid = nullptr) = 0;
   virtual hipError_t update(const Geo &g, const WS &w, hipStream_t st, int mode, int prec, int kind,
@@ -178,7 +179,8 @@ template <int NS, int NT> class Runner : public IRunner {
     if constexpr (NS >= BLOCK_NS_MIN) {
       if (flags & 2) {
         const BlockOut bo{{w.grp[0].S, w.grp[1].S}, w.Dinv, w.group_c, w.diag, w.sur.J, ddfail_counter(w.flags),
-                          w.flags + FL_SURR_OFF, w.flags + FL_SING, nullptr, 0, src_block ? w.R : nullptr, w.b};
+                          w.flags + FL_SURR_OFF, w.flags + FL_SING, nullptr, 0, SampleMap{0, 0},
+                          src_block ? w.R : nullptr, w.b};
         if (sur_ready) {
           const hipError_t e = hipStreamWaitEvent(st, sur_ready, 0);
           if (e != hipSuccess) return e;
@@ -217,15 +219,17 @@ template <int NS, int NT> class Runner : public IRunner {
     return hipGetLastError();
   }
 
-  hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc, int flags) override {
+  hipError_t sample(const Geo &g, const WS &w, hipStream_t st, int n, float *xr, float *jc, int flags,
+                    SampleMap sm) override {
     hipError_t e = prim(g, w, st, false, false);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_sample<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, xr, jc,
-                       flags);
+                       flags, sm);
     if constexpr (NS >= BLOCK_NS_MIN) {
       // the species rows from the block kernel (one lane per row)
-      hipLaunchKernelGGL((k_handoff<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, w.diag);
-      BlockOut bo{{nullptr, nullptr}, nullptr, 0, w.diag, nullptr, nullptr, nullptr, nullptr, jc, long(n)};
+      hipLaunchKernelGGL((k_handoff<NS, NT>), dim3(nblocks(n)), dim3(256), 0, st, g, w.mech, w.Q, w.prim, n, w.diag,
+                         sm);
+      BlockOut bo{{nullptr, nullptr}, nullptr, 0, w.diag, nullptr, nullptr, nullptr, nullptr, jc, long(n), sm};
       constexpr int C = BlockDims<NS, NT, 1>::C;
       hipLaunchKernelGGL((k_block<NS, NT, float, 1>), dim3(nblocks(n, C)), dim3(64), 0, st, g, w.mech, w.Q, w.prim,
                          2 | (flags & 24), bo, nullptr);

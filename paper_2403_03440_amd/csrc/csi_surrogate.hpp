@@ -27,16 +27,17 @@ __device__ inline double sur_feature(const double *__restrict__ prim, size_t NP,
 template <int NS, int NT>
 __global__ void __launch_bounds__(256) k_sample(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
                                                 const double *__restrict__ prim, int n, float *__restrict__ xr,
-                                                float *__restrict__ jc, int flags) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+                                                float *__restrict__ jc, int flags, SampleMap sm) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int p = int(sm(r, g.N));  // row r of the sample is cell p
   const Mech &m = *mech;
   const size_t NP = g.NP;
   const int i = p % g.ni, j = p / g.ni;
   const long pc = padc(g, i, j);
   constexpr int NIN = NS + 3;
 #pragma unroll
-  for (int k = 0; k < NIN; ++k) xr[long(p) * NIN + k] = float(sur_feature<NS, NT>(prim, NP, pc, k));
+  for (int k = 0; k < NIN; ++k) xr[long(r) * NIN + k] = float(sur_feature<NS, NT>(prim, NP, pc, k));
   // the block kernel writes J_C where it builds the species blocks
   if (NS >= BLOCK_NS_MIN) return;
   constexpr int NV = Dims<NS, NT>::nv;
@@ -59,8 +60,8 @@ __global__ void __launch_bounds__(256) k_sample(Geo g, const Mech *__restrict__ 
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
-    for (int r = 0; r < NS; ++r)
-      jc[long(p) * NS * NS + s * NS + r] = float(C.dw_dr[s][r] + C.dw_dT[s] * dTc[r] + C.dw_dTv[s] * dTvc[r]);
+    for (int c = 0; c < NS; ++c)
+      jc[long(r) * NS * NS + s * NS + c] = float(C.dw_dr[s][c] + C.dw_dT[s] * dTc[c] + C.dw_dTv[s] * dTvc[c]);
 }
 
 // sinh in FP32: the Taylor series to y^7 below |y| = 1/2 (truncation below

@@ -114,7 +114,7 @@ class WideRunner : public IRunner {
   }
 
   hipError_t surrogate(const Geo &, const WS &, hipStream_t, bool) override { return hipErrorNotSupported; }
-  hipError_t sample(const Geo &, const WS &, hipStream_t, int, float *, float *, int) override {
+  hipError_t sample(const Geo &, const WS &, hipStream_t, int, float *, float *, int, SampleMap) override {
     return hipErrorNotSupported;
   }
 

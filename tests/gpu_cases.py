@@ -151,3 +151,27 @@ def groups_inc(m, mode):
     n = m.nb if mode == 0 else nf + m.ns
     dens = [0] + list(range(nf, n))
     return [dens, [1, 2], [3] + ([4] if m.two_temp else [])]
+
+
+def sample_cells(N, n, seed):
+    """The cells of csi_sample_jacobians' rows, from the definition in csi.h:
+    every cell in order when n >= N, else row r is cell (b + r a) mod N with
+    b = splitmix64(seed) mod N and a the first value coprime with N from
+    1 + splitmix64(seed + 1) mod (N - 1) upwards, wrapping within [1, N - 1]."""
+    if n >= N:
+        return np.arange(N)
+    if N <= 1:
+        return np.zeros(n, dtype=np.int64)
+    mask = (1 << 64) - 1
+
+    def splitmix64(x):
+        z = (x + 0x9E3779B97F4A7C15) & mask
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        return z ^ (z >> 31)
+
+    b = splitmix64(seed & mask) % N
+    a = 1 + splitmix64((seed + 1) & mask) % (N - 1)
+    while np.gcd(a, N) != 1:
+        a = a % (N - 1) + 1
+    return np.array([(b + r * a) % N for r in range(n)], dtype=np.int64)

@@ -9,7 +9,7 @@ bound, all others to 2e-5 of the summed magnitudes."""
 import numpy as np
 import pytest
 
-from gpu_cases import mech_by_name, normwise, pair
+from gpu_cases import mech_by_name, normwise, pair, sample_cells
 from oracle import mlp
 from paper_2403_03440_amd import inputs as I
 
@@ -201,10 +201,18 @@ def test_sample_jacobians_parity(name, reading):
     Jg = jc.cpu().numpy().astype(np.float64)
     scale = np.abs(Jo).max(axis=1, keepdims=True) + 1e-300
     assert np.all(np.abs(Jg - Jo) <= 1e-6 * scale)
-    n = s.sample_jacobians(xr, jc, max_samples=100)
-    assert n == 100
-    Jg100 = jc[:100].cpu().numpy().astype(np.float64)
-    assert np.all(np.abs(Jg100 - Jo[:100]) <= 1e-6 * scale[:100])
+    # seeded subsets of 100 distinct cells (csi.h's definition of the rows)
+    subsets = []
+    for seed in (7, 3440):
+        n = s.sample_jacobians(xr, jc, max_samples=100, seed=seed)
+        assert n == 100
+        cells = sample_cells(N, 100, seed)
+        assert len(set(cells.tolist())) == 100
+        subsets.append(set(cells.tolist()))
+        Jg100 = jc[:100].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(Jg100 - Jo[cells]) <= 1e-6 * scale[cells])
+        assert normwise(xr[:100].cpu().numpy().T, xo[cells].T, fg).max() <= 1e-6
+    assert subsets[0] != subsets[1]
 
 
 def _oracle_scales(o, m):
