@@ -431,6 +431,67 @@ def cpu_baseline(I, cfg, m, budget_s=20.0, sample_grid=(128, 64)):
     return out
 
 
+def oracle_time_to_tol(csi, I, names, tol, max_iter, window=20, measure_cells=20000):
+    """The oracle's time to a tol drop of the density residual (split CC2,
+    FP64, from the free stream, on the host cores) beside the GPU's split FP64
+    and split mixed runs of the same config.  Configs of at most
+    measure_cells cells are run to tol and timed whole ("measured"); larger
+    ones are timed over a window of iterations after the CFL ramp and the
+    time is the GPU FP64 iteration count times the oracle's seconds per
+    iteration over the first `window` iterations ("projected": a full oracle
+    run would take hours)."""
+    import numpy as np
+    import torch
+    from oracle import orc
+    threads = oracle_threads()
+    rows = []
+    for name in names:
+        cfg = I.CONFIGS[name]
+        m = cfg.mechanism()
+        x, y = cfg.grid()
+        fs = I.freestream_prims(cfg, m)
+        N = cfg.ni * cfg.nj
+        row = {"config": name, "cells": N, "tol": tol, "oracle_threads": threads}
+        gpu_iters = None
+        for v, prec in (("gpu_split64", csi.FP64), ("gpu_splitmixed", csi.MIXED)):
+            s = new_solver(csi, I, cfg, m, x, y, fs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.step(1, 2, cfg.cfl, max_iter, precision=prec, cfl_ramp=cfg.ramp, tol=tol, check_every=50)
+            torch.cuda.synchronize()
+            row[v] = {"iters": st["iters"], "converged": bool(st["converged"]), "seconds": time.perf_counter() - t0}
+            if prec == csi.FP64:
+                gpu_iters = st["iters"]
+            del s
+            torch.cuda.empty_cache()
+        o = orc.setup((x, y), m, fs, threads=threads)
+        o.set_state(o.prim_to_cons(*I.initial_prims(cfg, m)))
+        if N <= measure_cells:
+            t0 = time.perf_counter()
+            done, r0, drop = 0, None, 1.0
+            while done < max_iter and drop > tol:
+                h = o.step(1, 2, cfg.cfl, 10, ramp=cfg.ramp, it0=done)
+                r0 = h[0, 0] if r0 is None else r0
+                k = np.nonzero(h[:, 0] / r0 <= tol)[0]
+                done += int(k[0]) + 1 if k.size else 10
+                drop = h[-1, 0] / r0 if not k.size else h[k[0], 0] / r0
+            row["oracle"] = {"kind": "measured", "iters": done, "seconds": time.perf_counter() - t0,
+                             "converged": bool(drop <= tol)}
+        else:
+            # the first `window` iterations from the free stream
+            t0 = time.perf_counter()
+            o.step(1, 2, cfg.cfl, window, ramp=cfg.ramp)
+            spi = (time.perf_counter() - t0) / window
+            row["oracle"] = {"kind": "projected", "seconds_per_iter": spi, "window": window,
+                             "iters": gpu_iters, "seconds": spi * gpu_iters}
+        row["oracle_over_gpu_splitmixed"] = row["oracle"]["seconds"] / row["gpu_splitmixed"]["seconds"]
+        print(f"# {name}: oracle {row['oracle']['kind']} {row['oracle']['seconds']:.1f} s, GPU split mixed "
+              f"{row['gpu_splitmixed']['seconds']:.2f} s", file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"metric": "time to a density-residual drop, the oracle (host cores) beside the GPU", "unit": "s",
+            "cpu": cpu_model(), "rows": rows}
+
+
 def copy_probe(gib=1.0, reps=3):
     """A plain device copy of known size, for scaling HBM byte counters."""
     import torch
@@ -534,6 +595,8 @@ def main():
                                                  "study (implicit iteration time of CI and CS in non-reacting flow) "
                                                  "instead of the workload above")
     ap.add_argument("--scaling-grid", type=int, default=16, help="cells per side of the species-count study's box")
+    ap.add_argument("--oracle-tol", default="", help="configs (e.g. c1,c2,c4): the oracle's time to --tol "
+                    "beside the GPU's (measured up to 20 000 cells, projected from a timed window above)")
     ap.add_argument("--residual", choices=("hlle", "muscl"), default="hlle",
                     help="residual scheme of the throughput and time-to-tolerance legs")
     ap.add_argument("--residual-ablation", default="", help="free-stream speeds (e.g. 2000,5000): MUSCL + Roe "
@@ -550,6 +613,10 @@ def main():
     if args.scaling:
         print(json.dumps(scaling(csi, I, [int(v) for v in args.scaling.split(",")], args.steps, args.warmup,
                                  args.scaling_grid)))
+        return
+    if args.oracle_tol:
+        print(json.dumps(oracle_time_to_tol(csi, I, [v for v in args.oracle_tol.split(",") if v], args.tol,
+                                            args.max_iter)))
         return
     if args.residual_ablation:
         config = args.config if args.config != "c5" else "c2"
