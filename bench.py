@@ -394,6 +394,30 @@ def cpu_model():
         return "unknown"
 
 
+def cpu_topology():
+    """Sockets, physical cores and logical CPUs of the host (/proc/cpuinfo),
+    and the logical CPUs this process may run on."""
+    out = {"sockets": None, "physical_cores": None, "logical_cpus": None,
+           "logical_cpus_visible": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            txt = f.read()
+    except OSError:
+        return out
+    procs = [blk for blk in txt.split("\n\n") if blk.strip()]
+    sockets, cores = set(), set()
+    for blk in procs:
+        kv = dict((ln.split(":", 1)[0].strip(), ln.split(":", 1)[1].strip()) for ln in blk.splitlines() if ":" in ln)
+        sockets.add(kv.get("physical id"))
+        cores.add((kv.get("physical id"), kv.get("core id")))
+    out["logical_cpus"] = len(procs)
+    if None not in sockets:
+        out["sockets"] = len(sockets)
+    if all(c[1] is not None for c in cores):
+        out["physical_cores"] = len(cores)
+    return out
+
+
 def cpu_baseline(I, cfg, m, budget_s=20.0, sample_grid=(128, 64)):
     """The oracle on the host cores over a bounded sample of the workload: the
     same mechanism, free stream and CFL schedule on a coarser grid of the same
@@ -424,7 +448,7 @@ def cpu_baseline(I, cfg, m, budget_s=20.0, sample_grid=(128, 64)):
            "sample": f"first {n} split-CC2 FP64 iterations from the free stream of the same mechanism, flow and "
                      f"CFL schedule on a {ni}x{nj} grid of the same geometry ({dt:.1f} s, {threads} OpenMP "
                      f"threads)",
-           "cpu": cpu_model(), "logical_cpus_visible": len(os.sched_getaffinity(0))}
+           "cpu": cpu_model(), **cpu_topology()}
     n1, dt1 = run(1, budget_s / 2, 50)
     out["value_1_thread"] = ni * nj * n1 / dt1
     out["sample_1_thread"] = f"first {n1} of the same iterations on 1 thread ({dt1:.1f} s)"
@@ -489,7 +513,7 @@ def oracle_time_to_tol(csi, I, names, tol, max_iter, window=20, measure_cells=20
               f"{row['gpu_splitmixed']['seconds']:.2f} s", file=sys.stderr, flush=True)
         rows.append(row)
     return {"metric": "time to a density-residual drop, the oracle (host cores) beside the GPU", "unit": "s",
-            "cpu": cpu_model(), "rows": rows}
+            "cpu": cpu_model(), **cpu_topology(), "rows": rows}
 
 
 def copy_probe(gib=1.0, reps=3):
