@@ -523,3 +523,23 @@ def test_sweep_cell_reproduces_the_sweeps(mode):
         i, j = p % 7, p // 7
         assert np.array_equal(o.sweep_cell(mode, 1, i, j, dqs), dqs[:, p])
         assert np.array_equal(o.sweep_cell(mode, 0, i, j, dqs, dq), dq[:, p])
+
+
+@pytest.mark.parametrize("mode,kind", [(orc.COUPLED, orc.CLOSURE), (orc.SPLIT, orc.CC2)])
+def test_threads_bitwise(mode, kind):
+    """The oracle's OpenMP loops (cells, faces, cells of one hyperplane) give
+    the same bits on 1 and on 8 threads: every cell's arithmetic is its own,
+    and the norms are summed in a fixed order."""
+    m = I.air5(1)
+    x, y = I.polar_grid(12, 9)
+    fs = (np.array([0.0, 0.0, 0.0, 0.233e-3, 0.767e-3]), 5000.0, 0.0, 250.0, 250.0)
+    res = []
+    for threads in (1, 8):
+        o = orc.setup((x, y), m, fs, threads=threads)
+        n = 12 * 9
+        o.set_state(o.prim_to_cons(np.repeat(fs[0][:, None], n, 1), np.full(n, fs[1]), np.zeros(n),
+                                   np.full(n, fs[3]), np.full(n, fs[4])))
+        h = o.step(mode, kind, 10.0, 15, ramp=15)
+        res.append((h, o.get_state()))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
