@@ -735,13 +735,16 @@ struct CellOut {
 // SRC_BLOCK (one temperature, ns >= BLOCK_NS_MIN, residual and diagonal in
 // one pass): the chemical source of R is added by the block kernel from its
 // reaction records, so this kernel forms the flux part only
-template <int NS, int NT, typename RT, bool SRC_BLOCK>
+// MODE: the form when fixed at compile time (0 coupled, 1 split), -1: the
+// `mode` argument
+template <int NS, int NT, typename RT, bool SRC_BLOCK, int MODE = -1>
 __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ mech, const double *__restrict__ Q,
                                               const double *__restrict__ prim, const double *__restrict__ Fi,
                                               const double *__restrict__ Fj, const double *__restrict__ Ri,
                                               const double *__restrict__ Rj, double cfl, int mode, int flags,
                                               CellOut out, const int *__restrict__ done) {
   using D = Dims<NS, NT>;
+  if (MODE >= 0) mode = MODE;
   constexpr int NV = D::nv, NB = D::nb, NF = D::nf;
   if (done && *done) return;
   __shared__ double red[2][256];

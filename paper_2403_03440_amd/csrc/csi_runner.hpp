@@ -159,15 +159,13 @@ template <int NS, int NT> class Runner : public IRunner {
     const bool src_block = SB && (flags & 3) == 3;
     if (prec == 0) {
       if (src_block)
-        hipLaunchKernelGGL((k_cell<NS, NT, double, SB>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim,
-                           w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+        launch_cell_sb<double>(g, w, st, cfl, mode, flags, o, done);
       else
         hipLaunchKernelGGL((k_cell<NS, NT, double, false>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q,
                            w.prim, w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
     } else {
       if (src_block)
-        hipLaunchKernelGGL((k_cell<NS, NT, float, SB>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim,
-                           w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+        launch_cell_sb<float>(g, w, st, cfl, mode, flags, o, done);
       else
         hipLaunchKernelGGL((k_cell<NS, NT, float, false>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q,
                            w.prim, w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
@@ -235,6 +233,20 @@ template <int NS, int NT> class Runner : public IRunner {
                          2 | (flags & 24), bo, nullptr);
     }
     return hipGetLastError();
+  }
+
+  // one temperature with the block kernel: the cell kernel compiled for the
+  // form at hand (each form's instantiation carries only its own branch)
+  template <typename RT>
+  static void launch_cell_sb(const Geo &g, const WS &w, hipStream_t st, double cfl, int mode, int flags,
+                             const CellOut &o, const int *done) {
+    constexpr bool SB = NT == 1 && NS >= BLOCK_NS_MIN;
+    if (mode == 1)
+      hipLaunchKernelGGL((k_cell<NS, NT, RT, SB, 1>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim,
+                         w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
+    else
+      hipLaunchKernelGGL((k_cell<NS, NT, RT, SB, 0>), dim3(w.nblk_cell), dim3(256), 0, st, g, w.mech, w.Q, w.prim,
+                         w.Fi, w.Fj, w.Ri, w.Rj, cfl, mode, flags, o, done);
   }
 
   template <typename RT, int MODE>
