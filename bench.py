@@ -624,7 +624,8 @@ def main():
     ap.add_argument("--residual", choices=("hlle", "muscl"), default="hlle",
                     help="residual scheme of the throughput and time-to-tolerance legs")
     ap.add_argument("--residual-ablation", default="", help="free-stream speeds (e.g. 2000,5000): MUSCL + Roe "
-                    "against HLLE, both forms, on --config (default c2 for this study) to --tol or --max-iter")
+                    "against HLLE, both forms, on --ablation-config to --tol or --max-iter")
+    ap.add_argument("--ablation-config", default="c2", help="workload of --residual-ablation")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this implementation runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -643,8 +644,8 @@ def main():
                                             args.max_iter)))
         return
     if args.residual_ablation:
-        config = args.config if args.config != "c5" else "c2"
-        print(json.dumps(residual_ablation(csi, I, config, [float(v) for v in args.residual_ablation.split(",")],
+        print(json.dumps(residual_ablation(csi, I, args.ablation_config,
+                                           [float(v) for v in args.residual_ablation.split(",")],
                                            args.max_iter, args.tol)))
         return
     cfg = I.CONFIGS[args.config]
