@@ -139,7 +139,8 @@ int csi_set_mechanism(csi_ctx *ctx, const csi_mechanism *m);
  * Only the residual changes: the implicit operator keeps its first-order
  * spectral-radius form.  A non-physical reconstructed state is reported as
  * CSI_ERR_NONFINITE by the residual or step.  Errors: CSI_ERR_ARG for another
- * value; CSI_ERR_UNSUPPORTED for 1 on the species-generic kernels. */
+ * value; CSI_ERR_UNSUPPORTED for 1 on the species-generic kernels (and
+ * csi_set_mechanism refuses those kernels while the scheme is 1). */
 int csi_set_residual_scheme(csi_ctx *ctx, int scheme);
 /* on = 1: the next csi_set_mechanism takes the species-generic kernels for
  * every species count (so that they can be compared with the compiled ones on

@@ -344,6 +344,8 @@ int csi_set_mechanism(csi_ctx *c, const csi_mechanism *mm) {
     if (mm->nr != 0 || mm->two_temp)
       return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels (ns = " + std::to_string(mm->ns) +
                                               ") take one temperature and no reactions");
+    if (c->scheme != 0)
+      return c->fail(CSI_ERR_UNSUPPORTED, "the species-generic kernels have the first-order residual only");
     r = make_wide_runner(mm, err);
     if (!r) return c->fail(CSI_ERR_ARG, "set_mechanism: " + err);
     std::memset(&c->mech, 0, sizeof(Mech));  // the generic runner reads its own table

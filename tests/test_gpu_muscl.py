@@ -168,3 +168,9 @@ def test_muscl_argument_errors():
     with pytest.raises(csi.CsiError, match="CSI_ERR_UNSUPPORTED"):
         sw.set_residual_scheme(MUSCL)
     sw.set_residual_scheme(0)
+    # and the other order: scheme 1 first, then the species-generic kernels
+    s.set_residual_scheme(MUSCL)
+    s.L.csi_set_species_generic(s.ctx, 1)
+    with pytest.raises(csi.CsiError, match="CSI_ERR_UNSUPPORTED"):
+        s.set_mechanism(base)
+    s.L.csi_set_species_generic(s.ctx, 0)
