@@ -119,6 +119,34 @@ def test_muscl_step_trajectory(mode, kind):
     assert np.all(normwise(s.get_state(), o.get_state(), groups_state(m)) <= 1e-9)
 
 
+def test_muscl_strong_shock_trajectory():
+    """c2's flow at 5 km/s (bow shock, H-correction active) on a 64 x 32
+    grid: 40 split FP64 iterations from the free stream with the CFL ramp
+    to 100, GPU against oracle."""
+    import dataclasses
+    csi = _csi()
+    cfg = dataclasses.replace(I.CONFIGS["c2"], ni=64, nj=32)
+    m = cfg.mechanism()
+    x, y = cfg.grid()
+    fs = I.freestream_prims(cfg, m)
+    o = orc.setup((x, y), m, fs, T_wall=cfg.T_wall)
+    q0 = o.prim_to_cons(*I.initial_prims(cfg, m))
+    s = csi.Solver((x, y), m, fs, T_wall=cfg.T_wall)
+    o.set_option("residual_scheme", MUSCL)
+    s.set_residual_scheme(MUSCL)
+    o.set_state(q0)
+    s.set_state(q0)
+    ho = o.step(1, 2, cfg.cfl, 40, ramp=cfg.ramp)
+    st = s.step(1, 2, cfg.cfl, 40, cfl_ramp=cfg.ramp, check_every=10)
+    assert st["iters"] == 40
+    hg = s.norm_history(40)
+    eh = np.abs(hg[:, 0] / ho[:, 0] - 1.0).max()
+    eq = normwise(s.get_state(), o.get_state(), groups_state(m)).max()
+    print(f"strong shock: history {eh:.2e}, state {eq:.2e}", flush=True)
+    assert eh <= 1e-9
+    assert eq <= 1e-9
+
+
 @pytest.mark.parametrize("ni,nj", [(1, 1), (1, 6), (7, 1), (2, 3), (33, 2)])
 def test_muscl_edge_shapes(ni, nj):
     csi = _csi()
