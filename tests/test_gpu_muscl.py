@@ -9,13 +9,15 @@ case (Section 3.2), built as a residual ablation.
   whatever the residual.  The bar is max(1e-12, 10 x the oracle's own
   sensitivity to rounding-level input changes), as for the first-order scheme.
 * Iterations: 30 ramped steps of each form at 2 km/s from the free stream
-  give the same norm history and state as the oracle's.  At that speed the
-  Roe flux on this grid has no carbuncle.
+  give the same norm history and state as the oracle's; so do 40 split
+  steps of c2's flow at 5 km/s on a 64 x 32 grid (bow shock, H-correction
+  active).
 * Degenerate grids (one row, one column, two cells across) and the
   far-field box: interior faces next to a boundary reconstruct from the
   ghost cell.
-* Argument errors: an unknown scheme gives CSI_ERR_ARG; scheme 1 on the
-  species-generic kernels gives CSI_ERR_UNSUPPORTED."""
+* Argument errors: an unknown scheme gives CSI_ERR_ARG; scheme 1 and the
+  species-generic kernels refuse each other (CSI_ERR_UNSUPPORTED) in either
+  order."""
 import numpy as np
 import pytest
 
