@@ -846,9 +846,12 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
     // coefficient of a): cell fields (m_x, m_y, u.m) and per lane
     //   g_k = [k > 0] u.m - c,  cp_k = (0, m_x, m_y, u.m, 0, ...)_k;
     // species part: u.m - c per face.
-    auto write_push = [&](int q, int part, int rv_lam, int rv_vis, const double *w, const double *ca) {
+    // partc: std::integral_constant of the part, so that the record shape,
+    // and with it the per-lane loop below, is known at compile time (the
+    // arrays w and ca then stay in registers)
+    auto write_push = [&](int q, auto partc, int rv_lam, int rv_vis, const double *w, const double *ca) {
       RT *St = reinterpret_cast<RT *>(out.gS[q]);
-      const RecShape S = rec_shape(part, NS, NT, sizeof(RT));
+      constexpr RecShape S = rec_shape(decltype(partc)::value, NS, NT, sizeof(RT));
       auto put = [&](int sec, int W, double v) { St[st_idx(S, g.N, sec, W, p)] = RT(v); };
       double mx[4], my[4], cf[4], un[4];
       mx[0] = -SEh * g.fi_nx[fE]; my[0] = -SEh * g.fi_ny[fE];
@@ -873,6 +876,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
         put(1 + f / 2, dw_m(S, f % 2) + 1, my[f]);
         put(1 + f / 2, dw_m(S, f % 2) + 2, un[f]);
       }
+#pragma unroll
       for (int k = 0; k < S.G; ++k) {
         put(0, rw_w(S, k), w[k]);
         put(0, rw_ca(S, k), ca[k]);
@@ -946,7 +950,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
             for (int c = 0; c < NB; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
           }
         }
-        write_push(0, PART_COUPLED, R_LAM, R_LVK, w, ca);
+        write_push(0, std::integral_constant<int, PART_COUPLED>{}, R_LAM, R_LVK, w, ca);
       }
     } else {
       double dF = Vdt + 0.5 * slam + svF;
@@ -1063,7 +1067,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
               for (int c = 0; c < NF; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Df[r][c]);
             }
           }
-          write_push(0, PART_FLOW, R_LAM, R_LVF, w, ca);
+          write_push(0, std::integral_constant<int, PART_FLOW>{}, R_LAM, R_LVF, w, ca);
         }
         // species part
         {
@@ -1077,7 +1081,7 @@ __global__ void __launch_bounds__(256) k_cell(Geo g, const Mech *__restrict__ me
               for (int c = 0; c < NS; ++c) St[st_idx(S, g.N, 0, rw_d(S, r, c), p)] = RT(Ai[r][c]);
             }
           }
-          write_push(1, PART_SPECIES, R_UABS, R_LVC, nullptr, nullptr);
+          write_push(1, std::integral_constant<int, PART_SPECIES>{}, R_UABS, R_LVC, nullptr, nullptr);
         }
       }
     }
